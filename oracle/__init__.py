@@ -1,0 +1,14 @@
+"""FP64 CPU reference oracle for the soft-shadow hot path (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
+leg may import this package.  It shares no code with the HIP library and never
+reads anything the GPU path produced.
+
+The numerics live in plain C (``oracle.c``, ``alternatives.c``), compiled with
+gcc into ``liboracle.so`` and called through ctypes; the reference gradient is
+torch float64 autograd (``grad_ref.py``).
+"""
+from .core import (  # noqa: F401
+    Params, build, load, maxmip_levels, maxmip, shadow, shadow_threaded, alternatives,
+    disc_fraction, schedule, ray_consts, probe, path_cells, TRACE_DTYPE,
+)

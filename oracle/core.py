@@ -1,0 +1,292 @@
+"""ctypes front end of the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+import threading
+import zlib
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "alternatives.c")]
+_lock = threading.RLock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (strict IEEE: no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", _SO + ".tmp"] + _SRC + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Params(C.Structure):
+    _fields_ = [("width", C.c_int32), ("rows", C.c_int32), ("texel_m", C.c_double),
+                ("radius_m", C.c_double), ("elev_rad", C.c_double), ("azim_rad", C.c_double),
+                ("ang_radius_rad", C.c_double), ("max_len_m", C.c_double),
+                ("n_prime0", C.c_int32), ("schedule", C.c_int32), ("n_segments", C.c_int32),
+                ("mode", C.c_int32), ("uniform_step", C.c_double),
+                ("uniform_tmax_m", C.c_double)]
+
+
+TRACE_DTYPE = np.dtype([("seg", np.int32), ("n", np.int32), ("t", np.float64),
+                        ("dh", np.float64), ("alpha", np.float64), ("base_i", np.int32),
+                        ("base_j", np.int32), ("evals", np.int32), ("margin_lb", np.float64),
+                        ("margin_dh", np.float64), ("margin_round", np.float64),
+                        ("margin_seg", np.float64), ("margin_geo", np.float64)], align=True)
+
+
+def load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_SO) or any(os.path.getmtime(s) > os.path.getmtime(_SO) for s in _SRC):
+            build()
+        lib = C.CDLL(_SO)
+        P = C.POINTER
+        lib.or_maxmip_levels.argtypes = [C.c_int32, C.c_int32]
+        lib.or_maxmip_levels.restype = C.c_int32
+        lib.or_maxmip_offset.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        lib.or_maxmip_offset.restype = C.c_int64
+        lib.or_maxmip_floats.argtypes = [C.c_int32, C.c_int32]
+        lib.or_maxmip_floats.restype = C.c_int64
+        lib.or_ctx_create.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        lib.or_ctx_create.restype = C.c_void_p
+        lib.or_ctx_destroy.argtypes = [C.c_void_p]
+        lib.or_ctx_destroy.restype = None
+        lib.or_ctx_copy_maxmip.argtypes = [C.c_void_p, C.c_void_p]
+        lib.or_ctx_copy_maxmip.restype = None
+        lib.or_shadow.argtypes = [C.c_void_p, P(_Params), C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]
+        lib.or_shadow.restype = C.c_int32
+        lib.or_alternatives.argtypes = [C.c_void_p, P(_Params), C.c_int64, C.c_double,
+                                        C.c_double, C.c_double, C.c_void_p, C.c_int32]
+        lib.or_alternatives.restype = C.c_int32
+        lib.or_disc_fraction.argtypes = [C.c_double]
+        lib.or_disc_fraction.restype = C.c_double
+        lib.or_schedule.argtypes = [P(_Params), C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.or_schedule.restype = C.c_int32
+        lib.or_ray_consts.argtypes = [C.c_void_p, P(_Params), C.c_int32, C.c_int32, C.c_void_p]
+        lib.or_ray_consts.restype = None
+        lib.or_probe.argtypes = [C.c_void_p, P(_Params), C.c_int32, C.c_int32, C.c_double,
+                                 C.c_void_p]
+        lib.or_probe.restype = None
+        lib.or_path_cells.argtypes = [C.c_void_p, P(_Params), C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int32]
+        lib.or_path_cells.restype = C.c_int32
+        _lib = lib
+        return lib
+
+
+@dataclass
+class Params:
+    """Problem statement of one (tile, sun) pair; angles in radians, lengths in metres."""
+    width: int
+    rows: int
+    texel_m: float
+    radius_m: float
+    elev: float
+    azim: float
+    ang_radius: float = math.radians(0.267)
+    max_len_m: float = 0.0
+    n_prime0: int = 5
+    schedule: int = 0
+    n_segments: int = 0
+    mode: int = 0
+    uniform_step: float = 1.0
+    uniform_tmax_m: float = 0.0
+
+    def c(self) -> _Params:
+        return _Params(self.width, self.rows, self.texel_m, self.radius_m, self.elev, self.azim,
+                       self.ang_radius, self.max_len_m, self.n_prime0, self.schedule,
+                       self.n_segments, self.mode, self.uniform_step, self.uniform_tmax_m)
+
+    def replace(self, **kw) -> "Params":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Params(**d)
+
+
+class _Ctx:
+    """Owns the oracle's maximum mipmap of one heightfield."""
+
+    def __init__(self, h: np.ndarray):
+        self.h = np.ascontiguousarray(h, dtype=np.float32)
+        self.lib = load()
+        rows, width = self.h.shape
+        self.ptr = self.lib.or_ctx_create(self.h.ctypes.data, width, rows)
+        if not self.ptr:
+            raise MemoryError("oracle context")
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            self.lib.or_ctx_destroy(self.ptr)
+            self.ptr = None
+
+
+_ctx_cache: dict = {}
+
+
+def _ctx(h: np.ndarray) -> _Ctx:
+    """Context for h, reused while the array's address, shape and contents are unchanged."""
+    key = (h.__array_interface__["data"][0], h.shape, zlib.crc32(memoryview(h).cast("B")))
+    with _lock:
+        c = _ctx_cache.get(key)
+        if c is None:
+            c = _Ctx(h)
+            _ctx_cache.clear()
+            _ctx_cache[key] = c
+    return c
+
+
+def maxmip_levels(width: int, rows: int) -> int:
+    return load().or_maxmip_levels(width, rows)
+
+
+def maxmip(h: np.ndarray) -> list:
+    """Levels 1..L-1 of the maximum mipmap as a list of float32 arrays."""
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    rows, width = h.shape
+    lib = load()
+    ctx = _ctx(h)
+    total = lib.or_maxmip_floats(width, rows)
+    flat = np.empty(max(total, 1), dtype=np.float32)
+    lib.or_ctx_copy_maxmip(ctx.ptr, flat.ctypes.data)
+    out = []
+    w, r = width, rows
+    for m in range(1, lib.or_maxmip_levels(width, rows)):
+        w, r = (w + 1) // 2, (r + 1) // 2
+        off = lib.or_maxmip_offset(width, rows, m)
+        out.append(flat[off:off + w * r].reshape(r, w).copy())
+    return out
+
+
+def shadow(h: np.ndarray, p: Params, rays=None, trace: bool = False, _c=None):
+    """Shadow factor s (float64) for all texels ([rows, width]) or the given linear indices."""
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    rows, width = h.shape
+    assert (p.width, p.rows) == (width, rows)
+    lib = load()
+    ctx = _c if _c is not None else _ctx(h)
+    if rays is None:
+        n = width * rows
+        rp = None
+    else:
+        rays = np.ascontiguousarray(rays, dtype=np.int64)
+        n = rays.size
+        rp = rays.ctypes.data
+    s = np.empty(n, dtype=np.float64)
+    alpha = np.empty(n, dtype=np.float64)
+    tr = np.empty(n, dtype=TRACE_DTYPE) if trace else None
+    pc = p.c()
+    rc = lib.or_shadow(ctx.ptr, C.byref(pc), rp, n, s.ctypes.data, alpha.ctypes.data,
+                       tr.ctypes.data if trace else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the problem ({rc})")
+    if rays is None:
+        s = s.reshape(rows, width)
+        alpha = alpha.reshape(rows, width)
+        if trace:
+            tr = tr.reshape(rows, width)
+    return (s, alpha, tr) if trace else (s, alpha)
+
+
+def shadow_threaded(h: np.ndarray, p: Params, rays=None, threads: int | None = None,
+                    trace: bool = False):
+    """Same as ``shadow`` over ray chunks on a thread pool (ctypes drops the GIL)."""
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    rows, width = h.shape
+    if rays is None:
+        rays_all = np.arange(width * rows, dtype=np.int64)
+    else:
+        rays_all = np.ascontiguousarray(rays, dtype=np.int64)
+    threads = threads or max(1, len(os.sched_getaffinity(0)))
+    c = _ctx(h)  # one mipmap shared by every thread
+    chunks = np.array_split(rays_all, max(1, threads * 4))
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda r: shadow(h, p, r, trace=trace, _c=c), chunks))
+    s = np.concatenate([q[0] for q in parts])
+    a = np.concatenate([q[1] for q in parts])
+    t = np.concatenate([q[2] for q in parts]) if trace else None
+    if rays is None:
+        s = s.reshape(rows, width)
+        a = a.reshape(rows, width)
+        if trace:
+            t = t.reshape(rows, width)
+    return (s, a, t) if trace else (s, a)
+
+
+def alternatives(h: np.ndarray, p: Params, ray: int, eps_lb: float, eps_dh: float,
+                 eps_t: float):
+    """Angular clearances valid for one ray under near-ties; None if the branch cap hit."""
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    lib = load()
+    ctx = _ctx(h)
+    out = np.empty(256, dtype=np.float64)
+    pc = p.c()
+    n = lib.or_alternatives(ctx.ptr, C.byref(pc), int(ray), eps_lb, eps_dh, eps_t,
+                            out.ctypes.data, 256)
+    if n == -2:
+        raise ValueError("bad ray or mode")
+    if n < 0:
+        return None
+    return out[:n].copy()
+
+
+def disc_fraction(d: float) -> float:
+    return load().or_disc_fraction(float(d))
+
+
+def schedule(p: Params):
+    """(m0 list, tau list, delta) of the segment schedule."""
+    lib = load()
+    m0 = np.zeros(64, dtype=np.int32)
+    tau = np.zeros(65, dtype=np.float64)
+    delta = C.c_double()
+    pc = p.c()
+    n = lib.or_schedule(C.byref(pc), m0.ctypes.data, tau.ctypes.data, C.byref(delta))
+    return m0[:n].tolist(), tau[:n + 1].tolist(), delta.value
+
+
+_CONST_NAMES = ["nx", "ny", "nz", "px", "py", "pz", "rho", "sp", "cp", "t_hmin", "texit",
+                "Lx", "Ly", "Lz", "delta", "hp"]
+
+
+def ray_consts(h: np.ndarray, p: Params, i: int, j: int) -> dict:
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    ctx = _ctx(h)
+    out = np.zeros(16, dtype=np.float64)
+    pc = p.c()
+    load().or_ray_consts(ctx.ptr, C.byref(pc), i, j, out.ctypes.data)
+    return dict(zip(_CONST_NAMES, out.tolist()))
+
+
+def probe(h: np.ndarray, p: Params, i: int, j: int, t: float) -> dict:
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    ctx = _ctx(h)
+    out = np.zeros(8, dtype=np.float64)
+    pc = p.c()
+    load().or_probe(ctx.ptr, C.byref(pc), i, j, float(t), out.ctypes.data)
+    k = ["qx", "qy", "H", "h_bil", "dh", "alpha", "inside", "texit"]
+    return dict(zip(k, out.tolist()))
+
+
+def path_cells(h: np.ndarray, p: Params, i: int, j: int, level: int, ta: float, tb: float):
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    ctx = _ctx(h)
+    cells = np.zeros(64, dtype=np.int32)
+    ts = np.zeros(64, dtype=np.float64)
+    pc = p.c()
+    n = load().or_path_cells(ctx.ptr, C.byref(pc), i, j, level, float(ta), float(tb),
+                             cells.ctypes.data, ts.ctypes.data, 32)
+    return [((int(cells[2 * k]), int(cells[2 * k + 1])), (float(ts[2 * k]), float(ts[2 * k + 1])))
+            for k in range(n)]

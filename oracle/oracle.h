@@ -1,0 +1,92 @@
+/* Reference oracle for the soft-shadow hot path: public C interface.
+ *
+ * TEST INFRASTRUCTURE.  This is a plain, slow FP64 CPU implementation written
+ * from the paper (Jung, Schrempp, Son: "Optimally Fast Soft Shadows on Curved
+ * Terrain with Dynamic Programming and Maximum Mipmaps").  Only the tests, the
+ * package smoke check and the bench's CPU-baseline leg may load it.  It shares
+ * no code, header, table or helper with the HIP library.
+ *
+ * Conventions: heights are float32, row-major [rows][width], metres above the
+ * reference sphere.  Texel (column i, row j) covers [i, i+1) x [j, j+1) in
+ * continuous texel coordinates; its centre is a ray origin.
+ */
+#ifndef SS_ORACLE_H
+#define SS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_MAXSEG 64
+#define OR_MAXLEV 32
+
+typedef struct {
+  int32_t width, rows;
+  double texel_m;         /* texel spacing on the tangent plane at the tile centre */
+  double radius_m;        /* body radius; +INFINITY selects the flat-plane mode */
+  double elev_rad;        /* sun elevation in the tile-centre frame */
+  double azim_rad;        /* sun azimuth from +column toward +row */
+  double ang_radius_rad;  /* apparent radius of the sun disc */
+  double max_len_m;       /* horizontal ray cap; <= 0: rays run to the tile edge */
+  int32_t n_prime0;       /* mip levels traced by the first segment */
+  int32_t schedule;       /* 0: N'_j = N'_0 + j (geometric); 1: N'_j = N'_0 (equal) */
+  int32_t n_segments;     /* > 0 overrides the segment count derived from the cap */
+  int32_t mode;           /* 0: dynamic-programming descent; 1: uniform stepping */
+  double uniform_step;    /* uniform step, texels of horizontal travel */
+  double uniform_tmax_m;  /* > 0 overrides the uniform cap on ray length t */
+} or_params;
+
+typedef struct {
+  int32_t seg;           /* segment that gave the minimum (uniform: -1); -2 when lit by default */
+  int32_t n;             /* index of the deciding sample on the t grid */
+  double t;              /* ray length of that sample */
+  double dh;             /* clearance height of that sample */
+  double alpha;          /* angular clearance (radians), +INF when no valid sample */
+  int32_t base_i, base_j;/* base texel of the descent in that segment */
+  int32_t evals;         /* lower-bound evaluations + final samples (uniform: steps) */
+  double margin_lb;      /* smallest best/runner-up gap of any lower-bound argmin (m) */
+  double margin_dh;      /* smallest best/runner-up gap of any final-sample argmin (m) */
+  double margin_round;   /* smallest distance of a rounding argument from its boundary */
+  double margin_seg;     /* gap between the two smallest segment clearances (rad) */
+  double margin_geo;     /* smallest spacing of crossing events, texels of travel */
+} or_trace;
+
+typedef struct or_ctx or_ctx;
+
+int32_t or_maxmip_levels(int32_t width, int32_t rows);
+int64_t or_maxmip_offset(int32_t width, int32_t rows, int32_t level); /* floats, levels >= 1 */
+int64_t or_maxmip_floats(int32_t width, int32_t rows);
+
+/* Builds the maximum mipmap of h (kept by reference: h must outlive the context). */
+or_ctx* or_ctx_create(const float* h, int32_t width, int32_t rows);
+void or_ctx_destroy(or_ctx* c);
+/* Copies levels >= 1 into out (layout of or_maxmip_offset). */
+void or_ctx_copy_maxmip(const or_ctx* c, float* out);
+
+/* Shadow factor for n_rays texels (linear index j*width+i; NULL = all texels
+ * in order).  s_out[k] in [0,1]; alpha_out and trace_out may be NULL. */
+int32_t or_shadow(const or_ctx* c, const or_params* p, const int64_t* rays, int64_t n_rays,
+                  double* s_out, double* alpha_out, or_trace* trace_out);
+
+/* Set of angular clearances the method yields for one ray when every decision
+ * whose FP64 margin is below the given tolerances may go either way.  Returns
+ * the number of values written (<= max_out), or -1 when the set exceeded the
+ * branch cap.  eps_lb/eps_dh in metres, eps_t in texels of travel. */
+int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray,
+                        double eps_lb, double eps_dh, double eps_t,
+                        double* alpha_out, int32_t max_out);
+
+/* Inspection helpers used by the pins. */
+double or_disc_fraction(double d);
+int32_t or_schedule(const or_params* p, int32_t* m0_out, double* tau_out, double* delta_out);
+void or_ray_consts(const or_ctx* c, const or_params* p, int32_t i, int32_t j, double* out16);
+void or_probe(const or_ctx* c, const or_params* p, int32_t i, int32_t j, double t, double* out8);
+int32_t or_path_cells(const or_ctx* c, const or_params* p, int32_t i, int32_t j, int32_t level,
+                      double ta, double tb, int32_t* cells_out, double* t_out, int32_t max_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,99 @@
+"""Pins of the reference gradient (torch float64 autograd along the oracle's
+branch) against central finite differences of the FP64 oracle forward.
+
+Texels whose +/- perturbation changes any ray's decision record (segment,
+final sample, base texel) are skipped: there the shadow factor is not
+differentiable.  The forward values along the branch must equal the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import grad_ref
+
+R = 1737400.0
+RL = math.radians(0.267)
+
+
+def terrain(shape, seed, amp):
+    rng = np.random.default_rng(seed)
+    rows, width = shape
+    y, x = np.mgrid[0:rows, 0:width].astype(np.float64)
+    h = np.zeros(shape)
+    for k in range(5):
+        f = rng.uniform(0.05, 0.3)
+        th = rng.uniform(0, 2 * math.pi)
+        h += amp / (k + 1) * np.sin(f * (x * math.cos(th) + y * math.sin(th)) + rng.uniform(0, 6))
+    return h.astype(np.float32)
+
+
+def key(tr):
+    return np.stack([tr["seg"], tr["n"], tr["base_i"], tr["base_j"]], axis=-1)
+
+
+@pytest.mark.parametrize("radius", [R, math.inf])
+def test_branch_forward_equals_oracle(orc, radius):
+    h = terrain((32, 40), 3, 60.0)
+    p = orc.Params(40, 32, 10.0, radius, math.radians(1.5), 0.8, RL)
+    s, _, tr = orc.shadow(h, p, trace=True)
+    _, _, _, s_b = grad_ref.reference_gradient(h, p, tr, np.zeros(s.size))
+    # |p + tL| - R cancels about 2e-10 m in FP64 on the Moon's radius, which is
+    # ~1e-8 in s for the first samples (t of a few metres); the plane is exact.
+    tol = 1e-12 if math.isinf(radius) else 1e-7
+    assert np.max(np.abs(s_b - s.reshape(-1))) < tol
+
+
+@pytest.mark.parametrize("radius", [R, math.inf])
+def test_height_gradient_matches_finite_differences(orc, radius):
+    rng = np.random.default_rng(4)
+    h = terrain((28, 28), 5, 40.0)
+    p = orc.Params(28, 28, 10.0, radius, math.radians(1.5), 2.1, RL)
+    s0, _, tr0 = orc.shadow(h, p, trace=True)
+    w = rng.standard_normal(s0.shape)
+    g_h, _, _, _ = grad_ref.reference_gradient(h, p, tr0, w)
+    eps = 1e-3
+    checked = 0
+    for lin in rng.permutation(h.size)[:40]:
+        j, i = divmod(int(lin), h.shape[1])
+        hp = h.copy()
+        hm = h.copy()
+        hp[j, i] += np.float32(eps)
+        hm[j, i] -= np.float32(eps)
+        dp_ = float(hp[j, i]) - float(h[j, i])
+        dm_ = float(h[j, i]) - float(hm[j, i])
+        sp, _, trp = orc.shadow(hp, p, trace=True)
+        sm, _, trm = orc.shadow(hm, p, trace=True)
+        if not (np.array_equal(key(trp), key(tr0)) and np.array_equal(key(trm), key(tr0))):
+            continue
+        fd = (np.sum(w * sp) - np.sum(w * sm)) / (dp_ + dm_)
+        assert abs(fd - g_h[j, i]) <= 1e-4 * max(1.0, abs(fd)), (i, j, fd, g_h[j, i])
+        checked += 1
+    assert checked >= 20
+
+
+@pytest.mark.parametrize("radius", [R, math.inf])
+def test_sun_gradient_matches_finite_differences(orc, radius):
+    rng = np.random.default_rng(6)
+    h = terrain((28, 28), 7, 40.0)
+    e0, a0 = math.radians(1.5), 2.1
+    p = orc.Params(28, 28, 10.0, radius, e0, a0, RL)
+    s0, _, tr0 = orc.shadow(h, p, trace=True)
+    w = rng.standard_normal(s0.shape)
+    _, g_e, g_a, _ = grad_ref.reference_gradient(h, p, tr0, w)
+    # the FP64 forward carries ~1e-8 of rounding in s (see above), so the step
+    # must be large enough for the difference quotient to rise above it
+    eps = 1e-5
+    for name, g in (("elev", g_e), ("azim", g_a)):
+        pp = p.replace(**{"elev" if name == "elev" else "azim": (e0 if name == "elev" else a0) + eps})
+        pm = p.replace(**{"elev" if name == "elev" else "azim": (e0 if name == "elev" else a0) - eps})
+        sp, _, trp = orc.shadow(h, pp, trace=True)
+        sm, _, trm = orc.shadow(h, pm, trace=True)
+        same = np.all(key(trp) == key(tr0), axis=-1) & np.all(key(trm) == key(tr0), axis=-1)
+        # rays whose decisions moved do not have a derivative; compare on the rest
+        ww = np.where(same, w, 0.0)
+        _, g_e2, g_a2, _ = grad_ref.reference_gradient(h, p, tr0, ww)
+        g = g_e2 if name == "elev" else g_a2
+        fd = (np.sum(ww * sp) - np.sum(ww * sm)) / (2 * eps)
+        assert abs(fd - g) <= 2e-4 * max(1.0, abs(fd)), (name, fd, g)
+        assert same.mean() > 0.8
