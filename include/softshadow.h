@@ -1,0 +1,157 @@
+/* softshadow: soft shadows on a planetary heightfield by dynamic programming
+ * over a maximum mipmap, after Jung, Schrempp and Son, "Optimally Fast Soft
+ * Shadows on Curved Terrain with Dynamic Programming and Maximum Mipmaps".
+ *
+ * C ABI of libsoftshadow.so (HIP, gfx950).  Conventions for every call:
+ *
+ *  - Heights are float32, row-major [rows][width], metres above a reference
+ *    sphere of radius body_radius_m.  Texel (column i, row j) covers
+ *    [i, i+1) x [j, j+1) in texel units and its centre is a ray origin.
+ *  - The tile is a gnomonic patch: the tile-centre frame has z along the local
+ *    vertical, x along +column, y along +row; the texel grid lies on the plane
+ *    tangent to the sphere at the tile centre and spacing texel_m is measured
+ *    there (Sec. 3.2, texture-space ray; Sec. 4, cube-sphere faces).
+ *  - Every pointer named d_* is DEVICE memory owned by the caller; the library
+ *    never frees it.  Host structs (ss_tile, ss_sun, ss_params) are read during
+ *    the call only.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *    work on it: they return before the GPU finishes and never synchronise the
+ *    device, except where a function says otherwise.
+ *  - Return value: SS_OK (0) or a negative SS_ERR_* status; arguments are
+ *    validated on the host before anything is enqueued, so an error leaves
+ *    every output untouched.  No C++ exception crosses the ABI.
+ *  - Calls are reentrant; calls that share output buffers must be ordered by
+ *    the caller (same stream or events).
+ */
+#ifndef SOFTSHADOW_H
+#define SOFTSHADOW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SS_OK 0
+#define SS_ERR_INVALID_ARG (-1)  /* a pointer, size or parameter is out of range */
+#define SS_ERR_HIP (-2)          /* the HIP runtime reported an error; see ss_status_string */
+#define SS_ERR_WORKSPACE (-3)    /* workspace missing or smaller than required */
+#define SS_ERR_UNSUPPORTED (-4)  /* a combination this build does not implement */
+
+#define SS_MODE_DP 0             /* dynamic-programming descent (Sec. 3.2, Alg. 1) */
+#define SS_MODE_UNIFORM 1        /* uniform stepping baseline (Sec. 2, Fig. 1b; Sec. 6.3) */
+
+#define SS_SCHED_GEOMETRIC 0     /* segment j traces N'_0 + j levels (capped at the mipmap) */
+#define SS_SCHED_EQUAL 1         /* every segment traces N'_0 levels (the paper's {5,5,5}) */
+
+/* Sun direction in the tile-centre frame (Sec. 3.1: shadow ray toward the disc
+ * centre; Sec. 3.4: apparent disc radius r_L).  |elev_rad| < pi/2; azimuth is
+ * measured from +column toward +row; ang_radius_rad > 0. */
+typedef struct {
+  double elev_rad;
+  double azim_rad;
+  double ang_radius_rad;
+} ss_sun;
+
+/* Method parameters.  Zero-initialised fields take the defaults noted. */
+typedef struct {
+  double body_radius_m;    /* > 0; INFINITY selects a flat plane (test geometry) */
+  double max_len_m;        /* horizontal ray cap; <= 0: rays run to the tile edge */
+  int32_t n_prime0;        /* levels of the first segment, N'_0 (Sec. 3.2; 0 -> 5) */
+  int32_t schedule;        /* SS_SCHED_* (Sec. 3.3 interval concatenation) */
+  int32_t n_segments;      /* > 0 fixes the number of concatenated runs; 0: reach max_len_m */
+  int32_t mode;            /* SS_MODE_* */
+  double uniform_step;     /* SS_MODE_UNIFORM: step in texels of horizontal travel, >= 1/64 (0 -> 1) */
+  int32_t prune;           /* 1: skip work that cannot change the result (bitwise-identical) */
+  int32_t ray_tile;        /* ray-tile shape code, 0 = default (results never depend on it) */
+} ss_params;
+
+/* One heightfield tile.  `maxmip` holds levels >= 1 of its maximum mipmap in
+ * the packed layout below (built by ss_maxmip_build). */
+typedef struct {
+  const float* height;     /* device, [rows][width] */
+  const float* maxmip;     /* device, ss_maxmip_floats(width, rows) floats */
+  int32_t width, rows;     /* >= 1 */
+  double texel_m;          /* > 0 */
+} ss_tile;
+
+/* ---- maximum mipmap (Sec. 3.2, "Maximum mipmaps") ------------------------ */
+
+/* Number of levels including level 0: 1 + ceil(log2(max(width, rows))).
+ * Returns 0 when a size is < 1. */
+int32_t ss_maxmip_levels(int32_t width, int32_t rows);
+
+/* Level m >= 1 has ceil(width/2^m) x ceil(rows/2^m) texels, row-major, starting
+ * at float offset ss_maxmip_level_offset(width, rows, m) (a multiple of 64).
+ * ss_maxmip_floats is the total size.  Invalid arguments give -1. */
+int64_t ss_maxmip_level_offset(int32_t width, int32_t rows, int32_t level);
+int64_t ss_maxmip_floats(int32_t width, int32_t rows);
+
+/* Builds levels >= 1: each texel is the maximum of the (up to four) texels it
+ * covers one level down; texels beyond a ragged edge are absent; -0 is stored
+ * as +0.  Bit-exact.  fuse_depth = levels written per launch (1..6, 0 = tuned).
+ * width or rows == 0 is an empty no-op. */
+int32_t ss_maxmip_build(const float* d_height, int32_t width, int32_t rows, float* d_maxmip,
+                        int32_t fuse_depth, void* stream);
+
+/* ---- shadow factor (Sec. 3.1-3.4, Alg. 1) -------------------------------- */
+
+/* For every texel centre p: cast the shadow ray p + t L toward the sun centre,
+ * find the clearance by the segment schedule (Sec. 3.3) and the descent through
+ * the maximum mipmap (Sec. 3.2) -- or by uniform steps in SS_MODE_UNIFORM --,
+ * and write the visible fraction of the sun disc (Sec. 3.4, Eq. 6 circular
+ * segment) to d_shadow[j*width + i] in [0, 1] (1 = fully lit).  Overwrites
+ * d_shadow.  tile->maxmip must hold the built mipmap of tile->height. */
+int32_t ss_shadow_cast(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                       float* d_shadow, void* stream);
+
+/* Instrumented variant: same output, and adds the number of lower-bound
+ * evaluations plus final samples (uniform: steps) to *d_eval_count. */
+int32_t ss_shadow_cast_counted(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                               float* d_shadow, unsigned long long* d_eval_count, void* stream);
+
+/* Adjoint of ss_shadow_cast (SS_MODE_DP only).  Recomputes every ray's
+ * decisions, then ACCUMULATES (+=) dL/dh into d_grad_height [rows][width] and
+ * dL/d(elev, azim) into d_grad_sun[2] (FP64), given dL/ds in d_grad_shadow.
+ * The max-mipmap enters only through discrete choices and has zero gradient.
+ * Accumulation uses atomics, so the summation order is not fixed. */
+int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                                const float* d_grad_shadow, float* d_grad_height,
+                                double* d_grad_sun, void* stream);
+
+/* ---- batched: many suns over tiles of uneven size ------------------------ */
+
+/* Bytes of device workspace ss_shadow_cast_batched needs (-1: bad sizes). */
+int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns);
+
+/* Builds every tile's maximum mipmap, then computes d_shadow[t*n_suns + k]
+ * (host array of device pointers, each [rows_t][width_t]) for tile t and sun
+ * k in one persistent launch that takes (tile, sun, ray block) items from a
+ * queue in d_workspace.  Outputs are bit-identical to ss_shadow_cast with the
+ * same parameters.  d_workspace is used for the duration of the call. */
+int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                               int32_t n_suns, const ss_params* params, float* const* d_shadow,
+                               void* d_workspace, int64_t workspace_bytes, void* stream);
+
+/* A captured HIP graph of the batched call for fixed buffers.  Create picks the
+ * ray-tile shape and mipmap fusion depth by timing the candidates on these
+ * inputs (it synchronises `stream` while tuning), then captures the maxmip
+ * builds and the persistent launch.  Launch replays the graph on `stream`; the
+ * workspace belongs to the plan until it is destroyed. */
+typedef struct ss_plan ss_plan;
+int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                               int32_t n_suns, const ss_params* params, float* const* d_shadow,
+                               void* d_workspace, int64_t workspace_bytes, void* stream,
+                               ss_plan** plan_out);
+int32_t ss_batched_plan_launch(ss_plan* plan, void* stream);
+/* The choices the tuner made: ray-tile code and fusion depth. */
+int32_t ss_batched_plan_config(const ss_plan* plan, int32_t* ray_tile, int32_t* fuse_depth);
+int32_t ss_batched_plan_destroy(ss_plan* plan);
+
+/* Text for a status code (for SS_ERR_HIP: the last HIP error of this thread). */
+const char* ss_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -22,10 +22,16 @@
 
 typedef struct {
   const ray_t* r;
-  double eps_lb, eps_dh, eps_t;
+  double eh_abs, eh_rel;  /* height tolerance: eh_abs + eh_rel * t (metres) */
+  double et_abs, et_rel;  /* position tolerance: et_abs + et_rel * t/delta (texels) */
   long budget;
   int overflow;
 } alt_t;
+
+static double eps_h(const alt_t* A, double t) { return A->eh_abs + A->eh_rel * fabs(t); }
+static double eps_t(const alt_t* A, double t) {
+  return A->et_abs + A->et_rel * fabs(t) / A->r->s->delta;
+}
 
 typedef struct {
   double v[ALT_MAXVALS];
@@ -180,7 +186,7 @@ static int cell_ok(const ray_t* r, int m, const cand_t* parent, int cx, int cy) 
 static int candidate_variants(alt_t* A, int m, double ta, double tb, const cand_t* parent,
                               cand_t lists[][OR_MAXCAND], int* counts) {
   const ray_t* r = A->r;
-  double w = A->eps_t * r->s->delta;
+  double w = eps_t(A, tb) * r->s->delta;
   piece_t pc[ALT_MAXPIECES];
   int np = build_pieces(r, m, ta, tb, w, pc);
   int amb[ALT_MAXPIECES], nopt[ALT_MAXPIECES], na = 0;
@@ -265,7 +271,7 @@ static void final_alternatives(alt_t* A, const cand_t* base, valset* out) {
   const setup_t* s = r->s;
   double tmid = 0.5 * (base->t_in + base->t_out);
   double arg = (tmid - s->tau0) / (0.5 * s->delta) + 0.5;
-  double ea = 2.0 * A->eps_t;
+  double ea = 2.0 * eps_t(A, tmid);
   long ncs[3];
   int nnc = 0;
   long nc = (long)floor(arg);
@@ -286,7 +292,7 @@ static void final_alternatives(alt_t* A, const cand_t* base, valset* out) {
       double qx, qy, Ht;
       or_ray_point(r, t, &qx, &qy, &Ht);
       double W = s->p->width, H = s->p->rows;
-      double e = A->eps_t;
+      double e = eps_t(A, t);
       int in = or_inside(s, qx, qy);
       double dmin = fmin(fmin(qx, W - qx), fmin(qy, H - qy));
       if (fabs(dmin) < e) st[q] = 2;
@@ -318,9 +324,10 @@ static void final_alternatives(alt_t* A, const cand_t* base, valset* out) {
       }
       for (int q = 0; q < 3; ++q) {
         if (!((mask >> q) & 1)) continue;
-        if (dh[q] <= best + A->eps_dh) {
-          vs_add(A, out, or_alpha_of(r, or_t_grid(s, nn[q]), dh[q]));
-          if (A->eps_dh == 0.0) break; /* exact ties keep the farther sample */
+        double tq = or_t_grid(s, nn[q]);
+        if (dh[q] <= best + eps_h(A, tq)) {
+          vs_add(A, out, or_alpha_of(r, tq, dh[q]));
+          if (eps_h(A, tq) == 0.0) break; /* exact ties keep the farther sample */
         }
       }
     }
@@ -341,9 +348,10 @@ static void descend(alt_t* A, int m, const cand_t* cands, int n, valset* out) {
   }
   if (n == 0) return;
   for (int k = n - 1; k >= 0; --k) {
-    int take = A->eps_lb > 0.0 ? lb[k] <= best + A->eps_lb : lb[k] == best;
+    double e = eps_h(A, cands[k].t_out);
+    int take = e > 0.0 ? lb[k] <= best + e : lb[k] == best;
     if (!take) continue;
-    if (A->eps_lb == 0.0) {
+    if (e == 0.0) {
       /* exact ties keep the farther texel: only the last minimum counts */
       int later = 0;
       for (int q = k + 1; q < n; ++q)
@@ -366,8 +374,8 @@ static void descend(alt_t* A, int m, const cand_t* cands, int n, valset* out) {
 static void segment_alternatives(alt_t* A, int jseg, valset* out) {
   const ray_t* r = A->r;
   const setup_t* s = r->s;
-  double w = A->eps_t * s->delta;
   double ta = s->tau[jseg];
+  double w = eps_t(A, ta) * s->delta;
   double tb = ta + ldexp(s->delta, s->m0[jseg]);
   if (r->texit - ta < w) vs_add(A, out, INFINITY);
   if (!(ta < r->texit + w)) return;
@@ -386,8 +394,9 @@ static void segment_alternatives(alt_t* A, int jseg, valset* out) {
   }
 }
 
-int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray, double eps_lb,
-                        double eps_dh, double eps_t, double* alpha_out, int32_t max_out) {
+int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray, double eh_abs,
+                        double eh_rel, double et_abs, double et_rel, double* alpha_out,
+                        int32_t max_out) {
   if (!c || !p || p->mode != 0) return -2;
   if (ray < 0 || ray >= (int64_t)c->W * c->H) return -2;
   setup_t s;
@@ -396,9 +405,10 @@ int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray, double
   or_ray_init(&r, &s, (int)(ray % c->W), (int)(ray / c->W));
   alt_t A;
   A.r = &r;
-  A.eps_lb = eps_lb;
-  A.eps_dh = eps_dh;
-  A.eps_t = eps_t;
+  A.eh_abs = eh_abs;
+  A.eh_rel = eh_rel;
+  A.et_abs = et_abs;
+  A.et_rel = et_rel;
   A.budget = 200000;
   A.overflow = 0;
   static __thread valset segs[OR_MAXSEG];

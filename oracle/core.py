@@ -69,7 +69,8 @@ def load():
                                   C.c_void_p, C.c_void_p]
         lib.or_shadow.restype = C.c_int32
         lib.or_alternatives.argtypes = [C.c_void_p, P(_Params), C.c_int64, C.c_double,
-                                        C.c_double, C.c_double, C.c_void_p, C.c_int32]
+                                        C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                        C.c_int32]
         lib.or_alternatives.restype = C.c_int32
         lib.or_disc_fraction.argtypes = [C.c_double]
         lib.or_disc_fraction.restype = C.c_double
@@ -225,15 +226,18 @@ def shadow_threaded(h: np.ndarray, p: Params, rays=None, threads: int | None = N
     return (s, a, t) if trace else (s, a)
 
 
-def alternatives(h: np.ndarray, p: Params, ray: int, eps_lb: float, eps_dh: float,
-                 eps_t: float):
-    """Angular clearances valid for one ray under near-ties; None if the branch cap hit."""
+def alternatives(h: np.ndarray, p: Params, ray: int, eh_abs: float, eh_rel: float = 0.0,
+                 et_abs: float = 0.0, et_rel: float = 0.0):
+    """Angular clearances valid for one ray under near-ties; None if the branch cap hit.
+
+    Height tolerance eh_abs + eh_rel*t (m), position tolerance et_abs + et_rel*t/delta
+    (texels), t the ray length at the decision."""
     h = np.ascontiguousarray(h, dtype=np.float32)
     lib = load()
     ctx = _ctx(h)
     out = np.empty(256, dtype=np.float64)
     pc = p.c()
-    n = lib.or_alternatives(ctx.ptr, C.byref(pc), int(ray), eps_lb, eps_dh, eps_t,
+    n = lib.or_alternatives(ctx.ptr, C.byref(pc), int(ray), eh_abs, eh_rel, et_abs, et_rel,
                             out.ctypes.data, 256)
     if n == -2:
         raise ValueError("bad ray or mode")

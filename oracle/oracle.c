@@ -163,12 +163,15 @@ void or_setup(setup_t* s, const or_ctx* c, const or_params* p) {
     if (j >= OR_MAXSEG) break;
   }
   s->nseg = j;
+  /* Uniform steps stop at the cap; without one at the tile edge, and at the
+   * latest after the tile diagonal (the segments' extent), since on the sphere
+   * a ray toward a texel's zenith never leaves the tile in texture space. */
   if (p->uniform_tmax_m > 0.0)
     s->tcap_uniform = p->uniform_tmax_m;
   else if (p->max_len_m > 0.0)
     s->tcap_uniform = p->max_len_m / p->texel_m * s->delta;
   else
-    s->tcap_uniform = INFINITY;
+    s->tcap_uniform = s->tau[s->nseg];
 }
 
 /* ------------------------------------------------------------------ */

@@ -71,11 +71,13 @@ int32_t or_shadow(const or_ctx* c, const or_params* p, const int64_t* rays, int6
                   double* s_out, double* alpha_out, or_trace* trace_out);
 
 /* Set of angular clearances the method yields for one ray when every decision
- * whose FP64 margin is below the given tolerances may go either way.  Returns
- * the number of values written (<= max_out), or -1 when the set exceeded the
- * branch cap.  eps_lb/eps_dh in metres, eps_t in texels of travel. */
+ * whose FP64 margin is below a tolerance may go either way.  Height margins
+ * (lower bounds, final clearances) use eh_abs + eh_rel * t metres, positions
+ * (crossings, rounding, tile edge) et_abs + et_rel * t/delta texels, t the
+ * ray length there.  Returns the number of values written (<= max_out), or -1
+ * when the branch cap was exceeded. */
 int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray,
-                        double eps_lb, double eps_dh, double eps_t,
+                        double eh_abs, double eh_rel, double et_abs, double et_rel,
                         double* alpha_out, int32_t max_out);
 
 /* Inspection helpers used by the pins. */

@@ -1,0 +1,293 @@
+"""Python binding of libsoftshadow: argument marshalling around the C ABI.
+
+Every step of the soft-shadow path runs in the HIP kernels; torch provides the
+device buffers and the current stream.  Names follow include/softshadow.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+SUN_RADIUS_RAD = math.radians(0.267)
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_f32_2d(h: torch.Tensor, name: str = "h") -> torch.Tensor:
+    if not isinstance(h, torch.Tensor) or h.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D tensor [rows, width]")
+    if not h.is_cuda or h.dtype != torch.float32 or not h.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return h
+
+
+@dataclass
+class Params:
+    """Method parameters (ss_params)."""
+    radius_m: float = 1737400.0
+    max_len_m: float = 0.0
+    n_prime0: int = 5
+    schedule: int = L.SS_SCHED_GEOMETRIC
+    n_segments: int = 0
+    mode: int = L.SS_MODE_DP
+    uniform_step: float = 1.0
+    prune: int = 1
+    ray_tile: int = 0
+
+    def c(self) -> L.SSParams:
+        return L.SSParams(float(self.radius_m), float(self.max_len_m), int(self.n_prime0),
+                          int(self.schedule), int(self.n_segments), int(self.mode),
+                          float(self.uniform_step), int(self.prune), int(self.ray_tile))
+
+
+def maxmip_levels(width: int, rows: int) -> int:
+    return L.lib().ss_maxmip_levels(width, rows)
+
+
+def maxmip_floats(width: int, rows: int) -> int:
+    return L.lib().ss_maxmip_floats(width, rows)
+
+
+def maxmip_level_offset(width: int, rows: int, level: int) -> int:
+    return L.lib().ss_maxmip_level_offset(width, rows, level)
+
+
+def maxmip(h: torch.Tensor, fuse_depth: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Levels >= 1 of the maximum mipmap of h, packed (ss_maxmip_level_offset)."""
+    _dev_f32_2d(h)
+    rows, width = h.shape
+    n = max(1, maxmip_floats(width, rows))
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=h.device)
+    elif out.numel() < n or out.dtype != torch.float32 or not out.is_cuda:
+        raise ValueError("out is too small or not float32 CUDA")
+    L.check("ss_maxmip_build", L.lib().ss_maxmip_build(h.data_ptr(), width, rows, out.data_ptr(),
+                                                       int(fuse_depth), _stream(h.device)))
+    return out
+
+
+def maxmip_unpack(mm: torch.Tensor, width: int, rows: int) -> list:
+    """Views of levels 1..L-1 of a packed mipmap as [rows_m, width_m] tensors."""
+    out = []
+    w, r = width, rows
+    for m in range(1, maxmip_levels(width, rows)):
+        w, r = (w + 1) // 2, (r + 1) // 2
+        off = maxmip_level_offset(width, rows, m)
+        out.append(mm[off:off + w * r].view(r, w))
+    return out
+
+
+def _tile(h: torch.Tensor, mm: torch.Tensor, texel_m: float) -> L.SSTile:
+    rows, width = h.shape
+    return L.SSTile(h.data_ptr(), mm.data_ptr(), width, rows, float(texel_m))
+
+
+def _sun(elev: float, azim: float, ang_radius: float) -> L.SSSun:
+    return L.SSSun(float(elev), float(azim), float(ang_radius))
+
+
+def shadow_cast(h: torch.Tensor, texel_m: float, elev: float, azim: float,
+                ang_radius: float = SUN_RADIUS_RAD, params: Params | None = None,
+                mm: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Shadow factor s in [0, 1] for every texel of h (builds the mipmap if mm is None)."""
+    _dev_f32_2d(h)
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    if out is None:
+        out = torch.empty_like(h)
+    t = _tile(h, mm, texel_m)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_cast", L.lib().ss_shadow_cast(C.byref(t), C.byref(s), C.byref(p),
+                                                     out.data_ptr(), _stream(h.device)))
+    return out
+
+
+def shadow_cast_counted(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=None, mm=None,
+                        out=None):
+    """(s, number of lower-bound evaluations + final samples) of one forward launch."""
+    _dev_f32_2d(h)
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    if out is None:
+        out = torch.empty_like(h)
+    cnt = torch.zeros(1, dtype=torch.int64, device=h.device)
+    t = _tile(h, mm, texel_m)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_cast_counted",
+            L.lib().ss_shadow_cast_counted(C.byref(t), C.byref(s), C.byref(p), out.data_ptr(),
+                                           cnt.data_ptr(), _stream(h.device)))
+    return out, cnt
+
+
+def shadow_cast_backward(h, texel_m, elev, azim, grad_s, ang_radius=SUN_RADIUS_RAD, params=None,
+                         mm=None, grad_h=None, grad_sun=None):
+    """Accumulates dL/dh (float32) and dL/d(elev, azim) (float64[2]) for upstream dL/ds."""
+    _dev_f32_2d(h)
+    _dev_f32_2d(grad_s, "grad_s")
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    if grad_h is None:
+        grad_h = torch.zeros_like(h)
+    if grad_sun is None:
+        grad_sun = torch.zeros(2, dtype=torch.float64, device=h.device)
+    t = _tile(h, mm, texel_m)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_cast_backward",
+            L.lib().ss_shadow_cast_backward(C.byref(t), C.byref(s), C.byref(p),
+                                            grad_s.data_ptr(), grad_h.data_ptr(),
+                                            grad_sun.data_ptr(), _stream(h.device)))
+    return grad_h, grad_sun
+
+
+class ShadowCast(torch.autograd.Function):
+    """s = shadow(h, elev, azim) with the hand-written adjoint kernel as backward.
+
+    h: float32 CUDA [rows, width]; elev, azim: 0-d float64 tensors (CPU or CUDA).
+    Gradients: dL/dh float32 (same device as h), dL/delev and dL/dazim float64.
+    """
+
+    @staticmethod
+    def forward(ctx, h, elev, azim, texel_m, ang_radius, params):
+        e = float(elev)
+        a = float(azim)
+        hd = h.detach().contiguous()
+        mm = maxmip(hd)
+        s = shadow_cast(hd, texel_m, e, a, ang_radius, params, mm=mm)
+        ctx.save_for_backward(hd, mm)
+        ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim)
+        return s
+
+    @staticmethod
+    def backward(ctx, grad_s):
+        hd, mm = ctx.saved_tensors
+        texel_m, e, a, ang_radius, params, elev, azim = ctx.cfg
+        g = grad_s.contiguous()
+        gh, gsun = shadow_cast_backward(hd, texel_m, e, a, g, ang_radius, params, mm=mm)
+        ge = gsun[0].to(elev.device) if isinstance(elev, torch.Tensor) else None
+        ga = gsun[1].to(azim.device) if isinstance(azim, torch.Tensor) else None
+        return gh, ge, ga, None, None, None
+
+
+def shadow(h, elev, azim, texel_m, ang_radius=SUN_RADIUS_RAD, params: Params | None = None):
+    """Differentiable shadow factor (see ShadowCast)."""
+    params = params or Params()
+    if not isinstance(elev, torch.Tensor):
+        elev = torch.tensor(float(elev), dtype=torch.float64)
+    if not isinstance(azim, torch.Tensor):
+        azim = torch.tensor(float(azim), dtype=torch.float64)
+    return ShadowCast.apply(h, elev, azim, texel_m, ang_radius, params)
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------
+
+def _batch_structs(heights, mms, texels, suns):
+    nt = len(heights)
+    tiles = (L.SSTile * max(1, nt))()
+    for k, (h, mm, tx) in enumerate(zip(heights, mms, texels)):
+        _dev_f32_2d(h, f"heights[{k}]")
+        tiles[k] = _tile(h, mm, tx)
+    ns = len(suns)
+    ss = (L.SSSun * max(1, ns))()
+    for k, sun in enumerate(suns):
+        e, a = sun[0], sun[1]
+        r = sun[2] if len(sun) > 2 else SUN_RADIUS_RAD
+        ss[k] = _sun(e, a, r)
+    return tiles, ss
+
+
+def batched_workspace_bytes(n_tiles: int, n_suns: int) -> int:
+    return L.lib().ss_batched_workspace_bytes(n_tiles, n_suns)
+
+
+def _alloc_batch(heights, suns, outs, mms):
+    dev = heights[0].device
+    if mms is None:
+        mms = [torch.empty(max(1, maxmip_floats(h.shape[1], h.shape[0])), dtype=torch.float32,
+                           device=dev) for h in heights]
+    if outs is None:
+        outs = [[torch.empty_like(h) for _ in suns] for h in heights]
+    ptrs = (C.c_void_p * max(1, len(heights) * len(suns)))()
+    for t in range(len(heights)):
+        for k in range(len(suns)):
+            o = outs[t][k]
+            _dev_f32_2d(o, "out")
+            if o.shape != heights[t].shape:
+                raise ValueError("output shape differs from its tile")
+            ptrs[t * len(suns) + k] = o.data_ptr()
+    ws = torch.empty(max(256, batched_workspace_bytes(len(heights), len(suns))), dtype=torch.uint8,
+                     device=dev)
+    return mms, outs, ptrs, ws
+
+
+def shadow_cast_batched(heights, texels, suns, params: Params | None = None, outs=None, mms=None):
+    """s for every (tile, sun): returns outs[t][k] (float32, shape of tile t).
+
+    Builds every tile's mipmap and runs one persistent launch over all items.
+    """
+    params = params or Params()
+    if len(heights) == 0 or len(suns) == 0:
+        return [[] for _ in heights]
+    mms, outs, ptrs, ws = _alloc_batch(heights, suns, outs, mms)
+    tiles, ss = _batch_structs(heights, mms, texels, suns)
+    p = params.c()
+    L.check("ss_shadow_cast_batched",
+            L.lib().ss_shadow_cast_batched(tiles, len(heights), ss, len(suns), C.byref(p),
+                                           ptrs, ws.data_ptr(), ws.numel(),
+                                           _stream(heights[0].device)))
+    return outs
+
+
+class BatchedPlan:
+    """Captured HIP graph of the batched call for fixed buffers (tuned at creation)."""
+
+    def __init__(self, heights, texels, suns, params: Params | None = None, outs=None, mms=None):
+        self.params = params or Params()
+        self.heights = list(heights)
+        self.mms, self.outs, self._ptrs, self.ws = _alloc_batch(self.heights, suns, outs, mms)
+        self._tiles, self._suns = _batch_structs(self.heights, self.mms, texels, suns)
+        self._p = self.params.c()
+        handle = C.c_void_p()
+        L.check("ss_batched_plan_create",
+                L.lib().ss_batched_plan_create(self._tiles, len(self.heights), self._suns,
+                                               len(suns), C.byref(self._p), self._ptrs,
+                                               self.ws.data_ptr(), self.ws.numel(),
+                                               _stream(self.heights[0].device), C.byref(handle)))
+        self._h = handle
+
+    def launch(self):
+        L.check("ss_batched_plan_launch",
+                L.lib().ss_batched_plan_launch(self._h, _stream(self.heights[0].device)))
+        return self.outs
+
+    def config(self):
+        rt = C.c_int32()
+        fd = C.c_int32()
+        L.check("ss_batched_plan_config", L.lib().ss_batched_plan_config(self._h, C.byref(rt),
+                                                                         C.byref(fd)))
+        return int(rt.value), int(fd.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().ss_batched_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

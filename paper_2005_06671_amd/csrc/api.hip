@@ -1,0 +1,641 @@
+// C ABI of libsoftshadow: validation, FP64 per-(tile, sun) set-up, launches,
+// the batched call and its captured-graph plan with the tuner.
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace ss;
+
+static thread_local hipError_t g_last_hip = hipSuccess;
+
+static int32_t hip_fail(hipError_t e) {
+  g_last_hip = e;
+  return SS_ERR_HIP;
+}
+
+#define SS_HIP(call)                         \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+// ------------------------------------------------------------------------
+// Mipmap layout: level m >= 1 at a 64-float aligned offset.
+// ------------------------------------------------------------------------
+
+static int levels_of(int32_t W, int32_t H) {
+  const int32_t big = W > H ? W : H;
+  int L = 1;
+  while ((1LL << (L - 1)) < big) L++;
+  return L;
+}
+
+static void dims_of(int32_t W, int32_t H, int m, int* w, int* h) {
+  int64_t a = W, b = H;
+  for (int k = 0; k < m; ++k) {
+    a = (a + 1) / 2;
+    b = (b + 1) / 2;
+  }
+  *w = (int)a;
+  *h = (int)b;
+}
+
+static bool size_ok(int32_t W, int32_t H) {
+  return W >= 1 && H >= 1 && W <= 65536 && H <= 65536 && (int64_t)W * H <= 2147483647LL;
+}
+
+extern "C" int32_t ss_maxmip_levels(int32_t width, int32_t rows) {
+  if (!size_ok(width, rows)) return 0;
+  return levels_of(width, rows);
+}
+
+extern "C" int64_t ss_maxmip_level_offset(int32_t width, int32_t rows, int32_t level) {
+  if (!size_ok(width, rows)) return -1;
+  const int L = levels_of(width, rows);
+  if (level < 1 || level > L) return -1;
+  int64_t off = 0;
+  for (int m = 1; m < level; ++m) {
+    int w, h;
+    dims_of(width, rows, m, &w, &h);
+    off += ((int64_t)w * h + 63) / 64 * 64;
+  }
+  return off;
+}
+
+extern "C" int64_t ss_maxmip_floats(int32_t width, int32_t rows) {
+  if (!size_ok(width, rows)) return -1;
+  return ss_maxmip_level_offset(width, rows, levels_of(width, rows));
+}
+
+static int32_t maxmip_build(const float* d_height, int32_t W, int32_t H, float* d_mm, int fuse,
+                            hipStream_t stream) {
+  const int L = levels_of(W, H);
+  if (fuse < 1 || fuse > 6) fuse = 6;
+  int src_m = 0;
+  while (src_m < L - 1) {
+    const int F = (L - 1 - src_m) < fuse ? (L - 1 - src_m) : fuse;
+    int sw, sh;
+    dims_of(W, H, src_m, &sw, &sh);
+    const float* src = src_m == 0 ? d_height : d_mm + ss_maxmip_level_offset(W, H, src_m);
+    int off[6], w[6], h[6];
+    for (int k = 0; k < F; ++k) {
+      off[k] = (int)ss_maxmip_level_offset(W, H, src_m + 1 + k);
+      dims_of(W, H, src_m + 1 + k, &w[k], &h[k]);
+    }
+    SS_HIP(launch_maxmip(src, sw, sh, d_mm, off, w, h, F, stream));
+    src_m += F;
+  }
+  return SS_OK;
+}
+
+extern "C" int32_t ss_maxmip_build(const float* d_height, int32_t width, int32_t rows,
+                                   float* d_maxmip, int32_t fuse_depth, void* stream) {
+  if (width == 0 || rows == 0) return (width >= 0 && rows >= 0) ? SS_OK : SS_ERR_INVALID_ARG;
+  if (!size_ok(width, rows) || !d_height) return SS_ERR_INVALID_ARG;
+  if (fuse_depth < 0 || fuse_depth > 6) return SS_ERR_INVALID_ARG;
+  if (ss_maxmip_floats(width, rows) > 0 && !d_maxmip) return SS_ERR_INVALID_ARG;
+  return maxmip_build(d_height, width, rows, d_maxmip, fuse_depth ? fuse_depth : 6,
+                      (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------------
+// Per-(tile, sun) set-up in FP64 (Sec. 3.3 schedule; Appendix step length).
+// ------------------------------------------------------------------------
+
+struct Resolved {
+  int n_prime0, schedule, n_segments, mode, prune, ray_tile;
+  double uniform_step;
+  bool sphere;
+};
+
+static int32_t resolve_params(const ss_params* p, Resolved* r) {
+  if (!p) return SS_ERR_INVALID_ARG;
+  if (!(p->body_radius_m > 0.0) || isnan(p->body_radius_m)) return SS_ERR_INVALID_ARG;
+  if (isnan(p->max_len_m) || isinf(p->max_len_m)) return SS_ERR_INVALID_ARG;
+  if (p->n_prime0 < 0 || p->n_prime0 > 64) return SS_ERR_INVALID_ARG;
+  if (p->schedule != SS_SCHED_GEOMETRIC && p->schedule != SS_SCHED_EQUAL) return SS_ERR_INVALID_ARG;
+  if (p->n_segments < 0) return SS_ERR_INVALID_ARG;
+  if (p->mode != SS_MODE_DP && p->mode != SS_MODE_UNIFORM) return SS_ERR_INVALID_ARG;
+  // 0 = default; otherwise at least 1/64 texel so the step count stays bounded
+  if (!(p->uniform_step == 0.0 || p->uniform_step >= 1.0 / 64.0) || isinf(p->uniform_step))
+    return SS_ERR_INVALID_ARG;
+  if (p->prune != 0 && p->prune != 1) return SS_ERR_INVALID_ARG;
+  if (p->ray_tile < 0 || p->ray_tile > SS_TILE_32x2) return SS_ERR_INVALID_ARG;
+  r->n_prime0 = p->n_prime0 ? p->n_prime0 : 5;
+  r->schedule = p->schedule;
+  r->n_segments = p->n_segments;
+  r->mode = p->mode;
+  r->prune = p->prune;
+  r->ray_tile = p->ray_tile ? p->ray_tile : SS_TILE_8x8;
+  r->uniform_step = p->uniform_step > 0.0 ? p->uniform_step : 1.0;
+  r->sphere = !isinf(p->body_radius_m);
+  return SS_OK;
+}
+
+static int32_t check_tile(const ss_tile* t) {
+  if (!t) return SS_ERR_INVALID_ARG;
+  if (t->width < 0 || t->rows < 0) return SS_ERR_INVALID_ARG;
+  if (t->width == 0 || t->rows == 0) return SS_OK;
+  if (!size_ok(t->width, t->rows) || !t->height) return SS_ERR_INVALID_ARG;
+  if (!(t->texel_m > 0.0) || isinf(t->texel_m)) return SS_ERR_INVALID_ARG;
+  if (ss_maxmip_floats(t->width, t->rows) > 0 && !t->maxmip) return SS_ERR_INVALID_ARG;
+  return SS_OK;
+}
+
+static int32_t check_sun(const ss_sun* s) {
+  if (!s) return SS_ERR_INVALID_ARG;
+  if (!(fabs(s->elev_rad) < 0.5 * M_PI)) return SS_ERR_INVALID_ARG;
+  if (!isfinite(s->azim_rad)) return SS_ERR_INVALID_ARG;
+  if (!(s->ang_radius_rad > 0.0) || !isfinite(s->ang_radius_rad)) return SS_ERR_INVALID_ARG;
+  return SS_OK;
+}
+
+static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp, double max_len_m,
+                          double radius, TileK* K) {
+  memset(K, 0, sizeof(*K));
+  const int W = t->width, H = t->rows;
+  const int L = levels_of(W, H);
+  if (L > SS_MAXLEV) return SS_ERR_UNSUPPORTED;
+  K->h = t->height;
+  K->mm = t->maxmip;
+  K->W = W;
+  K->H = H;
+  K->L = L;
+  for (int m = 0; m < L; ++m) {
+    dims_of(W, H, m, &K->lw[m], &K->lh[m]);
+    K->loff[m] = m == 0 ? 0 : (int)ss_maxmip_level_offset(W, H, m);
+  }
+  const double e = s->elev_rad, a = s->azim_rad;
+  const double ce = cos(e);
+  const double Lx = ce * cos(a), Ly = ce * sin(a), Lz = sin(e);
+  const double delta = t->texel_m / ce;  // ray length per texel of horizontal travel
+  K->texel = (float)t->texel_m;
+  K->invR = rp.sphere ? (float)(1.0 / radius) : 0.0f;
+  K->Lx = (float)Lx;
+  K->Ly = (float)Ly;
+  K->Lz = (float)Lz;
+  K->half_delta = (float)(0.5 * delta);
+  K->two_over_delta = (float)(2.0 / delta);
+  K->rL = (float)s->ang_radius_rad;
+  K->inv_rL = (float)(1.0 / s->ang_radius_rad);
+  K->prune_margin = 1e-5f;
+  K->prune = rp.prune;
+  K->ustep = (float)(rp.uniform_step * delta);
+
+  // concatenated runs: run j traces N'_j levels (top level N'_j - 1) and
+  // covers 2^(N'_j - 1) texels of travel; enough runs to reach the cap, or
+  // to span the tile diagonal without one
+  const double need = max_len_m > 0.0 ? max_len_m / t->texel_m
+                                      : sqrt((double)W * W + (double)H * H) + 2.0;
+  double tau = 0.5 * delta, covered = 0.0;
+  int j = 0;
+  K->tau[0] = (float)tau;
+  for (;;) {
+    if (j >= SS_MAXSEG) return SS_ERR_UNSUPPORTED;
+    int np = rp.schedule == SS_SCHED_EQUAL ? rp.n_prime0 : rp.n_prime0 + j;
+    if (np > L) np = L;
+    if (np < 1) np = 1;
+    K->m0[j] = np - 1;
+    tau += ldexp(delta, np - 1);
+    covered += ldexp(1.0, np - 1);
+    K->tau[j + 1] = (float)tau;
+    j++;
+    if (rp.n_segments > 0 ? j >= rp.n_segments : covered >= need) break;
+  }
+  K->nseg = j;
+  // uniform steps stop at the cap, or without one at the tile edge and at the
+  // latest after the runs' extent (the tile diagonal)
+  K->ucap = max_len_m > 0.0 ? (float)(max_len_m / t->texel_m * delta) : (float)tau;
+  if (rp.sphere) {
+    // the texture-space projection needs 1 + c t > 0 along every ray
+    const double half_ext = 0.5 * sqrt((double)W * W + (double)H * H) * t->texel_m;
+    const double cmax = fabs(Lz) * sqrt(1.0 + half_ext * half_ext / (radius * radius)) / radius * 1.01;
+    const double tmax = fmax(tau, (double)K->ucap);
+    if (Lz < 0.0 && isfinite(tmax) && cmax * tmax > 0.5) return SS_ERR_UNSUPPORTED;
+  }
+  return SS_OK;
+}
+
+// ------------------------------------------------------------------------
+// Per-tile entry points.
+// ------------------------------------------------------------------------
+
+static int32_t cast_common(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                           float* d_shadow, unsigned long long* counter, void* stream) {
+  int32_t rc = check_tile(tile);
+  if (rc) return rc;
+  if ((rc = check_sun(sun))) return rc;
+  Resolved rp;
+  if ((rc = resolve_params(params, &rp))) return rc;
+  if (tile->width == 0 || tile->rows == 0) return SS_OK;
+  if (!d_shadow) return SS_ERR_INVALID_ARG;
+  TileK K;
+  if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
+  SS_HIP(launch_forward(K, rp.sphere, rp.mode, rp.ray_tile, counter != nullptr, d_shadow, counter,
+                        (hipStream_t)stream));
+  return SS_OK;
+}
+
+extern "C" int32_t ss_shadow_cast(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                                  float* d_shadow, void* stream) {
+  return cast_common(tile, sun, params, d_shadow, nullptr, stream);
+}
+
+extern "C" int32_t ss_shadow_cast_counted(const ss_tile* tile, const ss_sun* sun,
+                                          const ss_params* params, float* d_shadow,
+                                          unsigned long long* d_eval_count, void* stream) {
+  if (!d_eval_count) return SS_ERR_INVALID_ARG;
+  return cast_common(tile, sun, params, d_shadow, d_eval_count, stream);
+}
+
+extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun,
+                                           const ss_params* params, const float* d_grad_shadow,
+                                           float* d_grad_height, double* d_grad_sun, void* stream) {
+  int32_t rc = check_tile(tile);
+  if (rc) return rc;
+  if ((rc = check_sun(sun))) return rc;
+  Resolved rp;
+  if ((rc = resolve_params(params, &rp))) return rc;
+  if (rp.mode != SS_MODE_DP) return SS_ERR_UNSUPPORTED;
+  if (tile->width == 0 || tile->rows == 0) return SS_OK;
+  if (!d_grad_shadow || !d_grad_height || !d_grad_sun) return SS_ERR_INVALID_ARG;
+  TileK K;
+  if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
+  SS_HIP(launch_adjoint(K, rp.sphere, sun->elev_rad, sun->azim_rad, d_grad_shadow, d_grad_height,
+                        d_grad_sun, (hipStream_t)stream));
+  return SS_OK;
+}
+
+// ------------------------------------------------------------------------
+// Batched form.
+// ------------------------------------------------------------------------
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct WsLayout {
+  size_t counter, pairs, outs, start, nbx, total;
+};
+
+static bool ws_layout(int32_t n_tiles, int32_t n_suns, WsLayout* L) {
+  if (n_tiles < 0 || n_suns < 0 || (int64_t)n_tiles * n_suns > 1000000) return false;
+  const size_t np = (size_t)n_tiles * n_suns;
+  L->counter = 0;
+  L->pairs = 256;
+  L->outs = L->pairs + align256(np * sizeof(TileK));
+  L->start = L->outs + align256(np * sizeof(float*));
+  L->nbx = L->start + align256((np + 1) * sizeof(long long));
+  L->total = L->nbx + align256(np * sizeof(int));
+  return true;
+}
+
+extern "C" int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns) {
+  WsLayout L;
+  if (!ws_layout(n_tiles, n_suns, &L)) return -1;
+  return (int64_t)L.total;
+}
+
+// Host image of the workspace tables (everything after the counter).
+struct BatchTables {
+  std::vector<unsigned char> bytes;  // laid out as WsLayout from offset L.pairs
+  BatchDesc bd;
+  Resolved rp;
+};
+
+static int32_t build_tables(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                            int32_t n_suns, const ss_params* params, float* const* d_shadow,
+                            int ray_tile, BatchTables* bt) {
+  int32_t rc;
+  if ((rc = resolve_params(params, &bt->rp))) return rc;
+  if (ray_tile) bt->rp.ray_tile = ray_tile;
+  WsLayout L;
+  if (!ws_layout(n_tiles, n_suns, &L)) return SS_ERR_INVALID_ARG;
+  const size_t np = (size_t)n_tiles * n_suns;
+  bt->bytes.assign(L.total - L.pairs, 0);
+  unsigned char* base = bt->bytes.data() - L.pairs;
+  TileK* pairs = reinterpret_cast<TileK*>(base + L.pairs);
+  float** outs = reinterpret_cast<float**>(base + L.outs);
+  long long* start = reinterpret_cast<long long*>(base + L.start);
+  int* nbxs = reinterpret_cast<int*>(base + L.nbx);
+  long long items = 0;
+  for (int t = 0; t < n_tiles; ++t) {
+    for (int k = 0; k < n_suns; ++k) {
+      const size_t p = (size_t)t * n_suns + k;
+      if ((rc = make_tilek(&tiles[t], &suns[k], bt->rp, params->max_len_m, params->body_radius_m,
+                           &pairs[p])))
+        return rc;
+      outs[p] = d_shadow[p];
+      int nbx, nb;
+      grid_for(pairs[p], bt->rp.ray_tile, &nbx, &nb);
+      nbxs[p] = nbx;
+      start[p] = items;
+      items += (nb + SS_ITEM_BLOCKS - 1) / SS_ITEM_BLOCKS;
+    }
+  }
+  start[np] = items;
+  bt->bd.n_pairs = (int)np;
+  bt->bd.n_tiles = n_tiles;
+  bt->bd.n_suns = n_suns;
+  bt->bd.total_items = items;
+  bt->bd.item_limit = items;
+  return SS_OK;
+}
+
+static int32_t check_batch(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns, int32_t n_suns,
+                           const ss_params* params, float* const* d_shadow, void* d_workspace,
+                           int64_t ws_bytes) {
+  if (n_tiles < 0 || n_suns < 0) return SS_ERR_INVALID_ARG;
+  if (n_tiles == 0 || n_suns == 0) return SS_OK;
+  if (!tiles || !suns || !params || !d_shadow) return SS_ERR_INVALID_ARG;
+  int32_t rc;
+  for (int t = 0; t < n_tiles; ++t) {
+    if ((rc = check_tile(&tiles[t]))) return rc;
+    if (tiles[t].width == 0 || tiles[t].rows == 0) return SS_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < n_suns; ++k)
+    if ((rc = check_sun(&suns[k]))) return rc;
+  for (int64_t p = 0; p < (int64_t)n_tiles * n_suns; ++p)
+    if (!d_shadow[p]) return SS_ERR_INVALID_ARG;
+  const int64_t need = ss_batched_workspace_bytes(n_tiles, n_suns);
+  if (need < 0) return SS_ERR_INVALID_ARG;
+  if (!d_workspace || ws_bytes < need) return SS_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return SS_ERR_WORKSPACE;
+  Resolved rp;
+  return resolve_params(params, &rp);
+}
+
+// Pinned staging for the tables of eager batched calls.
+static std::mutex g_stage_mu;
+static void* g_stage = nullptr;
+static size_t g_stage_cap = 0;
+static hipEvent_t g_stage_ev = nullptr;
+
+static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchTables& bt,
+                             unsigned char* ws, int fuse, int n_wg, hipStream_t stream) {
+  WsLayout L;
+  ws_layout(n_tiles, bt.bd.n_suns, &L);
+  for (int t = 0; t < n_tiles; ++t) {
+    int32_t rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows,
+                              const_cast<float*>(tiles[t].maxmip), fuse, stream);
+    if (rc) return rc;
+  }
+  SS_HIP(launch_fill_u32(reinterpret_cast<unsigned int*>(ws + L.counter), 0u, 1, stream));
+  SS_HIP(launch_batched(reinterpret_cast<const TileK*>(ws + L.pairs),
+                        reinterpret_cast<float* const*>(ws + L.outs),
+                        reinterpret_cast<const long long*>(ws + L.start),
+                        reinterpret_cast<const int*>(ws + L.nbx),
+                        reinterpret_cast<unsigned int*>(ws + L.counter), bt.bd, bt.rp.sphere,
+                        bt.rp.mode, bt.rp.ray_tile, n_wg, stream));
+  return SS_OK;
+}
+
+extern "C" int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                                          int32_t n_suns, const ss_params* params,
+                                          float* const* d_shadow, void* d_workspace,
+                                          int64_t workspace_bytes, void* stream) {
+  int32_t rc = check_batch(tiles, n_tiles, suns, n_suns, params, d_shadow, d_workspace,
+                           workspace_bytes);
+  if (rc) return rc;
+  if (n_tiles == 0 || n_suns == 0) return SS_OK;
+  BatchTables bt;
+  if ((rc = build_tables(tiles, n_tiles, suns, n_suns, params, d_shadow, 0, &bt))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* ws = static_cast<unsigned char*>(d_workspace);
+  WsLayout L;
+  ws_layout(n_tiles, n_suns, &L);
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    if (!g_stage_ev) SS_HIP(hipEventCreateWithFlags(&g_stage_ev, hipEventDisableTiming));
+    SS_HIP(hipEventSynchronize(g_stage_ev));  // the previous call's copy has left the buffer
+    if (g_stage_cap < bt.bytes.size()) {
+      if (g_stage) SS_HIP(hipHostFree(g_stage));
+      g_stage = nullptr;
+      g_stage_cap = 0;
+      SS_HIP(hipHostMalloc(&g_stage, bt.bytes.size(), hipHostMallocDefault));
+      g_stage_cap = bt.bytes.size();
+    }
+    memcpy(g_stage, bt.bytes.data(), bt.bytes.size());
+    SS_HIP(hipMemcpyAsync(ws + L.pairs, g_stage, bt.bytes.size(), hipMemcpyHostToDevice, s));
+    SS_HIP(hipEventRecord(g_stage_ev, s));
+  }
+  const int n_wg = batched_workgroups(bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile);
+  return enqueue_batch(tiles, n_tiles, bt, ws, 6, n_wg, s);
+}
+
+// ------------------------------------------------------------------------
+// Tuner and captured plan.
+// ------------------------------------------------------------------------
+
+struct TuneKey {
+  std::string s;
+  bool operator<(const TuneKey& o) const { return s < o.s; }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<int, int>> g_tune;
+
+static std::string tune_key(const ss_tile* tiles, int n_tiles, int n_suns, const Resolved& rp,
+                            const ss_params* p) {
+  char buf[128];
+  std::string k;
+  snprintf(buf, sizeof buf, "m%d s%d n%d g%d q%d r%.3g c%.3g|", rp.mode, rp.sphere, rp.n_prime0,
+           rp.schedule, rp.prune, p->body_radius_m, p->max_len_m);
+  k += buf;
+  for (int t = 0; t < n_tiles; ++t) {
+    snprintf(buf, sizeof buf, "%dx%d@%.4g,", tiles[t].width, tiles[t].rows, tiles[t].texel_m);
+    k += buf;
+  }
+  snprintf(buf, sizeof buf, "|%d", n_suns);
+  return k + buf;
+}
+
+static double time_ms(hipStream_t s, hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  hipEventSynchronize(b);
+  hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+// Times each ray-tile shape on the largest tile with its middle sun, and each
+// fusion depth on that tile's mipmap; the choices never change results.
+static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n_suns,
+                    const ss_params* params, const Resolved& rp, float* const* d_shadow,
+                    hipStream_t s, int* best_tile, int* best_fuse) {
+  int big = 0;
+  for (int t = 1; t < n_tiles; ++t)
+    if ((int64_t)tiles[t].width * tiles[t].rows > (int64_t)tiles[big].width * tiles[big].rows) big = t;
+  const int ks = n_suns / 2;
+  hipEvent_t a, b;
+  SS_HIP(hipEventCreate(&a));
+  SS_HIP(hipEventCreate(&b));
+  float* out = d_shadow[(size_t)big * n_suns + ks];
+  // fusion depth
+  double best = 1e30;
+  *best_fuse = 6;
+  const int fuses[4] = {6, 5, 4, 3};
+  for (int f : fuses) {
+    for (int rep = 0; rep < 3; ++rep) {
+      SS_HIP(hipEventRecord(a, s));
+      int32_t rc = maxmip_build(tiles[big].height, tiles[big].width, tiles[big].rows,
+                                const_cast<float*>(tiles[big].maxmip), f, s);
+      if (rc) return rc;
+      SS_HIP(hipEventRecord(b, s));
+      const double ms = time_ms(s, a, b);
+      if (rep > 0 && ms < best) {
+        best = ms;
+        *best_fuse = f;
+      }
+    }
+  }
+  // ray-tile shape
+  best = 1e30;
+  *best_tile = SS_TILE_8x8;
+  const int shapes[4] = {SS_TILE_8x8, SS_TILE_16x4, SS_TILE_4x16, SS_TILE_32x2};
+  Resolved r2 = rp;
+  for (int sh : shapes) {
+    r2.ray_tile = sh;
+    TileK K;
+    int32_t rc = make_tilek(&tiles[big], &suns[ks], r2, params->max_len_m, params->body_radius_m, &K);
+    if (rc) return rc;
+    for (int rep = 0; rep < 2; ++rep) {
+      SS_HIP(hipEventRecord(a, s));
+      SS_HIP(launch_forward(K, r2.sphere, r2.mode, sh, false, out, nullptr, s));
+      SS_HIP(hipEventRecord(b, s));
+      const double ms = time_ms(s, a, b);
+      if (rep > 0 && ms < best) {
+        best = ms;
+        *best_tile = sh;
+      }
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return SS_OK;
+}
+
+struct ss_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int ray_tile = 0, fuse = 0;
+};
+
+extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                                          int32_t n_suns, const ss_params* params,
+                                          float* const* d_shadow, void* d_workspace,
+                                          int64_t workspace_bytes, void* stream,
+                                          ss_plan** plan_out) {
+  if (!plan_out) return SS_ERR_INVALID_ARG;
+  *plan_out = nullptr;
+  int32_t rc = check_batch(tiles, n_tiles, suns, n_suns, params, d_shadow, d_workspace,
+                           workspace_bytes);
+  if (rc) return rc;
+  if (n_tiles == 0 || n_suns == 0) return SS_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  Resolved rp;
+  resolve_params(params, &rp);
+  // tune (mipmaps first: the ray kernels read them)
+  for (int t = 0; t < n_tiles; ++t) {
+    rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows,
+                      const_cast<float*>(tiles[t].maxmip), 6, s);
+    if (rc) return rc;
+  }
+  int tile_code = params->ray_tile, fuse = 6;
+  const std::string key = tune_key(tiles, n_tiles, n_suns, rp, params);
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{key});
+    if (it != g_tune.end()) {
+      if (!tile_code) tile_code = it->second.first;
+      fuse = it->second.second;
+      cached = true;
+    }
+  }
+  if (!cached) {
+    int bt_code = 0, bf = 6;
+    rc = tune(tiles, n_tiles, suns, n_suns, params, rp, d_shadow, s, &bt_code, &bf);
+    if (rc) return rc;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[TuneKey{key}] = {bt_code, bf};
+    }
+    if (!tile_code) tile_code = bt_code;
+    fuse = bf;
+  }
+  BatchTables bt;
+  if ((rc = build_tables(tiles, n_tiles, suns, n_suns, params, d_shadow, tile_code, &bt))) return rc;
+  unsigned char* ws = static_cast<unsigned char*>(d_workspace);
+  WsLayout L;
+  ws_layout(n_tiles, n_suns, &L);
+  SS_HIP(hipStreamSynchronize(s));
+  SS_HIP(hipMemcpy(ws + L.pairs, bt.bytes.data(), bt.bytes.size(), hipMemcpyHostToDevice));
+  const int n_wg = batched_workgroups(bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile);
+  ss_plan* plan = new ss_plan();
+  plan->ray_tile = tile_code;
+  plan->fuse = fuse;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete plan;
+    return hip_fail(e);
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = enqueue_batch(tiles, n_tiles, bt, ws, fuse, n_wg, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (rc == SS_OK && e2 != hipSuccess) rc = hip_fail(e2);
+    plan->graph = g;
+    if (rc == SS_OK) {
+      e2 = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+      if (e2 != hipSuccess) rc = hip_fail(e2);
+    }
+  } else {
+    rc = hip_fail(e);
+  }
+  hipStreamDestroy(cs);
+  if (rc != SS_OK) {
+    ss_batched_plan_destroy(plan);
+    return rc;
+  }
+  *plan_out = plan;
+  return SS_OK;
+}
+
+extern "C" int32_t ss_batched_plan_launch(ss_plan* plan, void* stream) {
+  if (!plan || !plan->exec) return SS_ERR_INVALID_ARG;
+  SS_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+  return SS_OK;
+}
+
+extern "C" int32_t ss_batched_plan_config(const ss_plan* plan, int32_t* ray_tile, int32_t* fuse_depth) {
+  if (!plan) return SS_ERR_INVALID_ARG;
+  if (ray_tile) *ray_tile = plan->ray_tile;
+  if (fuse_depth) *fuse_depth = plan->fuse;
+  return SS_OK;
+}
+
+extern "C" int32_t ss_batched_plan_destroy(ss_plan* plan) {
+  if (!plan) return SS_OK;
+  if (plan->exec) hipGraphExecDestroy(plan->exec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  delete plan;
+  return SS_OK;
+}
+
+extern "C" const char* ss_status_string(int32_t status) {
+  switch (status) {
+    case SS_OK: return "ok";
+    case SS_ERR_INVALID_ARG: return "invalid argument";
+    case SS_ERR_HIP: return g_last_hip == hipSuccess ? "HIP error" : hipGetErrorString(g_last_hip);
+    case SS_ERR_WORKSPACE: return "workspace missing or too small";
+    case SS_ERR_UNSUPPORTED: return "unsupported parameter combination";
+    default: return "unknown status";
+  }
+}

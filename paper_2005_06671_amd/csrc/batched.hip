@@ -1,0 +1,138 @@
+// Persistent batched kernel: many suns over tiles of uneven size in one launch.
+//
+// Items are (tile, sun, group of ray blocks) in tile-major, sun-minor order;
+// a workgroup takes the next item from a device counter (one atomic per item,
+// issued by one lane and broadcast through LDS) until the queue is empty, so
+// every workgroup reaches the exit.  Per-(tile, sun) parameter blocks live in
+// the workspace; the item index is wave-uniform, so they are read with scalar
+// loads.  Each ray runs the same device code as the per-tile kernel, so the
+// outputs are bit-identical to it.
+#include "kernels.h"
+#include "ray.h"
+
+namespace ss {
+
+__device__ __forceinline__ int pair_of(const long long* __restrict__ start, int n_pairs, long long item) {
+  int lo = 0, hi = n_pairs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <bool SPHERE, int TW, int MODE>
+__global__ __launch_bounds__(256) void batched_kernel(const TileK* __restrict__ pairs,
+                                                      float* const* __restrict__ outs,
+                                                      const long long* __restrict__ item_start,
+                                                      const int* __restrict__ pair_nbx,
+                                                      unsigned int* __restrict__ counter,
+                                                      long long item_limit, int n_pairs) {
+  constexpr int TH = 64 / TW;
+  __shared__ unsigned int s_item;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const long long item = (long long)s_item;
+    __syncthreads();
+    if (item >= item_limit) break;
+    const int pair = __builtin_amdgcn_readfirstlane(pair_of(item_start, n_pairs, item));
+    const TileK& T = pairs[pair];
+    float* out = outs[pair];
+    const int nbx = pair_nbx[pair];
+    const long long first = (item - item_start[pair]) * SS_ITEM_BLOCKS;
+    const long long nblk = (long long)nbx * ((T.H + 2 * TH - 1) / (2 * TH));
+    for (int g = 0; g < SS_ITEM_BLOCKS; ++g) {
+      const long long blk = first + g;
+      if (blk >= nblk) break;
+      const int bxi = (int)(blk % nbx), byi = (int)(blk / nbx);
+      const int i = bxi * (2 * TW) + (wave & 1) * TW + lane % TW;
+      const int j = byi * (2 * TH) + (wave >> 1) * TH + lane / TW;
+      if (i < T.W && j < T.H) {
+        const float hp = T.h[j * T.W + i];
+        Ray<SPHERE> r;
+        ray_init(T, i, j, hp, r);
+        const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
+        unsigned evals = 0;
+        float alpha;
+        if (MODE == SS_MODE_DP)
+          alpha = shadow_dp(T, r, top, evals).alpha;
+        else
+          alpha = shadow_uniform(T, r, top, evals);
+        out[j * T.W + i] = disc_fraction(alpha, T);
+      }
+    }
+  }
+}
+
+__global__ void fill_u32_kernel(unsigned int* p, unsigned int v, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, p, v, n);
+  return hipGetLastError();
+}
+
+template <bool SPHERE, int TW, int MODE>
+static hipError_t launch_b(const TileK* d_pairs, float* const* d_out, const long long* d_start,
+                           const int* d_nbx, unsigned int* d_counter, const BatchDesc& bd,
+                           int n_wg, hipStream_t stream) {
+  hipLaunchKernelGGL((batched_kernel<SPHERE, TW, MODE>), dim3(n_wg), dim3(256), 0, stream, d_pairs,
+                     d_out, d_start, d_nbx, d_counter, bd.item_limit, bd.n_pairs);
+  return hipGetLastError();
+}
+
+template <bool SPHERE, int MODE>
+static hipError_t launch_bm(const TileK* a, float* const* b, const long long* c, const int* d,
+                            unsigned int* e, const BatchDesc& bd, int ray_tile, int n_wg,
+                            hipStream_t s) {
+  switch (ray_tile) {
+    case SS_TILE_16x4: return launch_b<SPHERE, 16, MODE>(a, b, c, d, e, bd, n_wg, s);
+    case SS_TILE_4x16: return launch_b<SPHERE, 4, MODE>(a, b, c, d, e, bd, n_wg, s);
+    case SS_TILE_32x2: return launch_b<SPHERE, 32, MODE>(a, b, c, d, e, bd, n_wg, s);
+    default: return launch_b<SPHERE, 8, MODE>(a, b, c, d, e, bd, n_wg, s);
+  }
+}
+
+hipError_t launch_batched(const TileK* d_pairs, float* const* d_out_ptrs, const long long* d_item_start,
+                          const int* d_pair_nbx, unsigned int* d_counter, const BatchDesc& bd,
+                          bool sphere, int mode, int ray_tile, int n_workgroups, hipStream_t stream) {
+  if (bd.item_limit <= 0 || n_workgroups <= 0) return hipSuccess;
+  if (sphere)
+    return mode == SS_MODE_DP
+               ? launch_bm<true, SS_MODE_DP>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream)
+               : launch_bm<true, SS_MODE_UNIFORM>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream);
+  return mode == SS_MODE_DP
+             ? launch_bm<false, SS_MODE_DP>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream)
+             : launch_bm<false, SS_MODE_UNIFORM>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream);
+}
+
+// Workgroups that fit on the device at once for the chosen variant.
+int batched_workgroups(bool sphere, int mode, int ray_tile) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* fn = nullptr;
+#define SS_PICK(S, T, M) reinterpret_cast<const void*>(&batched_kernel<S, T, M>)
+  const int tw = ray_tile == SS_TILE_16x4 ? 16 : ray_tile == SS_TILE_4x16 ? 4 : ray_tile == SS_TILE_32x2 ? 32 : 8;
+  if (sphere) {
+    if (mode == SS_MODE_DP)
+      fn = tw == 16 ? SS_PICK(true, 16, 0) : tw == 4 ? SS_PICK(true, 4, 0) : tw == 32 ? SS_PICK(true, 32, 0) : SS_PICK(true, 8, 0);
+    else
+      fn = tw == 16 ? SS_PICK(true, 16, 1) : tw == 4 ? SS_PICK(true, 4, 1) : tw == 32 ? SS_PICK(true, 32, 1) : SS_PICK(true, 8, 1);
+  } else {
+    if (mode == SS_MODE_DP)
+      fn = tw == 16 ? SS_PICK(false, 16, 0) : tw == 4 ? SS_PICK(false, 4, 0) : tw == 32 ? SS_PICK(false, 32, 0) : SS_PICK(false, 8, 0);
+    else
+      fn = tw == 16 ? SS_PICK(false, 16, 1) : tw == 4 ? SS_PICK(false, 4, 1) : tw == 32 ? SS_PICK(false, 32, 1) : SS_PICK(false, 8, 1);
+  }
+#undef SS_PICK
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
+  return ncu * per;
+}
+
+}  // namespace ss

@@ -1,0 +1,37 @@
+// Parameter block shared by the host set-up and the gfx950 kernels.
+//
+// The host forms every per-(tile, sun) quantity in FP64 and rounds it once to
+// FP32 here; the kernels work in FP32 relative to each ray's origin.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SS_MAXLEV 18   // supports max(width, rows) <= 65536
+#define SS_MAXSEG 48   // concatenated runs per ray
+
+struct TileK {
+  const float* h;            // level 0: the heightfield, [H][W]
+  const float* mm;           // levels >= 1, packed at loff[m]
+  int W, H, L;               // size and number of mip levels (incl. level 0)
+  int lw[SS_MAXLEV], lh[SS_MAXLEV];
+  int loff[SS_MAXLEV];       // float offset of level m >= 1 inside mm
+  float texel;               // texel spacing on the tangent plane (m)
+  float invR;                // 1 / body radius (0 on the plane)
+  float Lx, Ly, Lz;          // unit vector toward the sun centre, tile frame
+  float half_delta;          // delta/2, delta = texel / cos(elev): first sample and grid step
+  float two_over_delta;      // 2 / delta
+  float rL, inv_rL;          // sun disc angular radius and its inverse
+  float prune_margin;        // safety margin (rad) of the result-invariant exits
+  float ustep;               // uniform stepping: step in ray length (m)
+  float ucap;                // uniform stepping: cap on ray length (m), +inf = tile edge
+  int nseg;                  // number of concatenated runs
+  int m0[SS_MAXSEG];         // top mip level of run j
+  float tau[SS_MAXSEG + 1];  // ray length where run j starts (tau[nseg] = end)
+  int prune;                 // 1: result-invariant early exits enabled
+  int pad_;
+};
+
+// Ray tile shapes: lanes of one wavefront cover TW x TH texels (TW * TH = 64),
+// a 256-thread workgroup covers 2 x 2 wavefront tiles.
+enum { SS_TILE_8x8 = 1, SS_TILE_16x4 = 2, SS_TILE_4x16 = 3, SS_TILE_32x2 = 4 };

@@ -1,0 +1,36 @@
+// Host-side launchers of the gfx950 kernels (internal to libsoftshadow).
+#pragma once
+
+#include "../../include/softshadow.h"
+#include "common.h"
+
+namespace ss {
+
+// Maximum mipmap: levels [m_src+1, m_src+F] from level m_src (F <= 6).
+hipError_t launch_maxmip(const float* src, int sw, int sh, float* dst_base, const int* dst_off,
+                         const int* dst_w, const int* dst_h, int F, hipStream_t stream);
+
+void grid_for(const TileK& T, int ray_tile, int* nbx, int* nblocks);
+
+hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, bool count,
+                          float* out, unsigned long long* counter, hipStream_t stream);
+
+hipError_t launch_adjoint(const TileK& T, bool sphere, double elev, double azim, const float* gs,
+                          float* gh, double* gsun, hipStream_t stream);
+
+// Persistent batched launch over (tile, sun, ray block) items.
+struct BatchDesc {
+  int n_pairs;            // tiles * suns
+  int n_tiles, n_suns;
+  long long total_items;  // sum over pairs of ray blocks
+  long long item_limit;   // process items [0, item_limit) (tuning); = total_items normally
+};
+hipError_t launch_batched(const TileK* d_pairs, float* const* d_out_ptrs, const long long* d_item_start,
+                          const int* d_pair_nbx, unsigned int* d_counter, const BatchDesc& bd,
+                          bool sphere, int mode, int ray_tile, int n_workgroups, hipStream_t stream);
+hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream);
+int batched_workgroups(bool sphere, int mode, int ray_tile);
+
+#define SS_ITEM_BLOCKS 4  // ray blocks (256 rays each) per queue item of the batched kernel
+
+}  // namespace ss

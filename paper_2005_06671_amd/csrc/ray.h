@@ -1,0 +1,378 @@
+// Per-ray device code: geometry, the descent through the maximum mipmap,
+// final samples, clearance angle and disc occlusion.  Used by the forward,
+// adjoint and persistent kernels, so every caller makes the same decisions.
+//
+// Everything is FP32 and relative to the ray origin p (texel centre):
+//   * texture-space offsets  d(u) = K u  with  u = t / (1 + c t)  (central
+//     projection maps the straight ray to a straight texture line);
+//   * tip height above p     dH(t) = t (2 s + x) / (sqrt(1 + x (2 s + x)) + 1),
+//     x = t / rho, the cancellation-free form of |p + t L| - |p|;
+//   * bilinear heights minus h_p.
+// Absolute coordinates would lose the metre-scale detail near the origin
+// (an FP32 ulp at the Moon's radius is 0.125 m).
+#pragma once
+
+#include "common.h"
+
+#define SS_INF __builtin_inff()
+
+__device__ __forceinline__ float ss_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float ss_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+template <bool SPHERE>
+struct Ray {
+  int i, j;
+  float hp;          // origin height
+  float Kx, Ky;      // texture-space velocity per unit u (texels)
+  float invKx, invKy;
+  float c;           // projective constant: u = t / (1 + c t)
+  float sp, cp;      // n.L and |n x L| at the origin (radial normal n)
+  float invrho;      // 1 / |p|
+  float uexit;       // u where the path leaves the tile
+  float uhmin;       // u where the tip height is smallest (-inf: rising from the start)
+  int sx, sy;        // direction of travel along columns / rows
+};
+
+template <bool SPHERE>
+__device__ __forceinline__ void ray_init(const TileK& T, int i, int j, float hp, Ray<SPHERE>& r) {
+  r.i = i;
+  r.j = j;
+  r.hp = hp;
+  const float X = ((float)i + 0.5f - 0.5f * (float)T.W) * T.texel;
+  const float Y = ((float)j + 0.5f - 0.5f * (float)T.H) * T.texel;
+  if (SPHERE) {
+    // n = (a, b, 1)/g with a = X/R, b = Y/R, g = |(a, b, 1)|; rho = R (1 + h_p/R)
+    const float a = X * T.invR, b = Y * T.invR;
+    const float g = sqrtf(1.0f + a * a + b * b);
+    const float ig = 1.0f / g;
+    const float r1 = 1.0f + hp * T.invR;
+    r.sp = (a * T.Lx + b * T.Ly + T.Lz) * ig;
+    const float cx = b * T.Lz - T.Ly, cy = T.Lx - a * T.Lz, cz = a * T.Ly - b * T.Lx;
+    r.cp = sqrtf(cx * cx + cy * cy + cz * cz) * ig;
+    const float sc = g / (r1 * T.texel);
+    r.Kx = (T.Lx - a * T.Lz) * sc;
+    r.Ky = (T.Ly - b * T.Lz) * sc;
+    r.c = T.Lz * g / r1 * T.invR;
+    r.invrho = T.invR / r1;
+    // |p + t L| is smallest at t = -rho s (ahead of p only when the sun is
+    // below the local horizon)
+    if (r.sp < 0.0f) {
+      const float th = -r.sp / r.invrho;
+      r.uhmin = th / (1.0f + r.c * th);
+    } else {
+      r.uhmin = -SS_INF;
+    }
+  } else {
+    r.sp = T.Lz;
+    r.cp = sqrtf(T.Lx * T.Lx + T.Ly * T.Ly);
+    r.Kx = T.Lx / T.texel;
+    r.Ky = T.Ly / T.texel;
+    r.c = 0.0f;
+    r.invrho = 0.0f;
+    r.uhmin = T.Lz >= 0.0f ? -SS_INF : SS_INF;
+  }
+  r.sx = r.Kx > 0.0f ? 1 : (r.Kx < 0.0f ? -1 : 0);
+  r.sy = r.Ky > 0.0f ? 1 : (r.Ky < 0.0f ? -1 : 0);
+  r.invKx = r.sx ? 1.0f / r.Kx : 0.0f;
+  r.invKy = r.sy ? 1.0f / r.Ky : 0.0f;
+  // leaving the tile: first boundary in the direction of travel
+  float ux = SS_INF, uy = SS_INF;
+  if (r.sx > 0) ux = ((float)(T.W - i) - 0.5f) / r.Kx;
+  if (r.sx < 0) ux = ((float)(-i) - 0.5f) / r.Kx;
+  if (r.sy > 0) uy = ((float)(T.H - j) - 0.5f) / r.Ky;
+  if (r.sy < 0) uy = ((float)(-j) - 0.5f) / r.Ky;
+  r.uexit = fminf(ux, uy);
+}
+
+template <bool SPHERE>
+__device__ __forceinline__ float u_to_t(const Ray<SPHERE>& r, float u) {
+  return SPHERE ? u * ss_rcp(1.0f - r.c * u) : u;
+}
+
+template <bool SPHERE>
+__device__ __forceinline__ float t_to_u(const Ray<SPHERE>& r, float t) {
+  return SPHERE ? t * ss_rcp(1.0f + r.c * t) : t;
+}
+
+// Tip height above the origin height: |p + t L| - |p| (sphere), t L_z (plane).
+template <bool SPHERE>
+__device__ __forceinline__ float tip_rise(const Ray<SPHERE>& r, const TileK& T, float t) {
+  if (SPHERE) {
+    const float x = t * r.invrho;
+    const float q = 2.0f * r.sp + x;
+    return t * q * ss_rcp(ss_sqrt(1.0f + x * q) + 1.0f);
+  }
+  return t * T.Lz;
+}
+
+__device__ __forceinline__ const float* level_ptr(const TileK& T, int m) {
+  return m == 0 ? T.h : T.mm + T.loff[m];
+}
+
+__device__ __forceinline__ float mip_at(const TileK& T, int m, int cx, int cy) {
+  const int w = T.lw[m], hgt = T.lh[m];
+  cx = min(max(cx, 0), w - 1);
+  cy = min(max(cy, 0), hgt - 1);
+  return level_ptr(T, m)[cy * w + cx];
+}
+
+// Lower bound of the clearance over the part [u0, u1] of the ray inside a
+// level-m texel: smallest tip height there minus the texel's maximum height
+// (Sec. 3.2, Eq. 4 with the maximum mipmap), relative to h_p.
+template <bool SPHERE>
+__device__ __forceinline__ float lower_bound(const Ray<SPHERE>& r, const TileK& T, int m, int cx,
+                                             int cy, float u0, float u1) {
+  const float uc = fminf(fmaxf(r.uhmin, u0), u1);
+  const float t = u_to_t(r, uc);
+  return tip_rise(r, T, t) - (mip_at(T, m, cx, cy) - r.hp);
+}
+
+// Bilinear sample of the terrain below the ray tip at ray length t (u = u(t)):
+// clearance height and the tap layout (for the adjoint).
+struct Sample {
+  float dh;
+  float fx, fy;
+  int x0, y0;   // unclamped lower-left tap (texel indices)
+};
+
+template <bool SPHERE>
+__device__ __forceinline__ Sample sample_at(const Ray<SPHERE>& r, const TileK& T, float t, float u) {
+  Sample s;
+  const float dx = r.Kx * u, dy = r.Ky * u;
+  const float flx = floorf(dx), fly = floorf(dy);
+  s.fx = dx - flx;
+  s.fy = dy - fly;
+  s.x0 = r.i + (int)flx;
+  s.y0 = r.j + (int)fly;
+  const int x0 = min(max(s.x0, 0), T.W - 1), x1 = min(max(s.x0 + 1, 0), T.W - 1);
+  const int y0 = min(max(s.y0, 0), T.H - 1), y1 = min(max(s.y0 + 1, 0), T.H - 1);
+  const float* h = T.h;
+  const float h00 = h[y0 * T.W + x0] - r.hp, h10 = h[y0 * T.W + x1] - r.hp;
+  const float h01 = h[y1 * T.W + x0] - r.hp, h11 = h[y1 * T.W + x1] - r.hp;
+  const float hb = (1.0f - s.fy) * ((1.0f - s.fx) * h00 + s.fx * h10) +
+                   s.fy * ((1.0f - s.fx) * h01 + s.fx * h11);
+  s.dh = tip_rise(r, T, t) - hb;
+  return s;
+}
+
+// Signed angle at p between L and the terrain point below the ray tip
+// (positive: below the ray).  First order: (dh / t) |n x L| (Sec. 3.4, Eq. 5).
+template <bool SPHERE>
+__device__ __forceinline__ float clearance(const Ray<SPHERE>& r, float t, float dh) {
+  if (SPHERE) {
+    const float x = t * r.invrho;
+    const float w = ss_sqrt(1.0f + x * (2.0f * r.sp + x));
+    return atan2f(dh * r.cp, t * w - dh * (r.sp + x));
+  }
+  return atan2f(dh * r.cp, t - dh * r.sp);
+}
+
+// Visible part of the sun disc above a chord at d disc radii below its centre
+// (Sec. 3.4, Eq. 6 first term; circular segment).
+__device__ __forceinline__ float disc_fraction(float alpha, const TileK& T) {
+  if (!(alpha < SS_INF)) return 1.0f;
+  const float d = fminf(fmaxf(alpha * T.inv_rL, -1.0f), 1.0f);
+  return (3.14159265358979f - acosf(d) + d * sqrtf(fmaxf(0.0f, 1.0f - d * d))) *
+         0.318309886183791f;
+}
+
+struct SegOut {
+  float alpha;
+  float t;        // ray length of the deciding sample
+  float u;
+  int valid;
+};
+
+// One concatenated run (Sec. 3.3): descent from level m0 = T.m0[j] over the
+// texels the ray crosses (Sec. 3.2, Fig. 3b), strict argmin from the far end
+// (kept here as '<=' scanning from the near end), then three samples half a
+// texel apart around the chosen base texel (Alg. 1, final level).
+template <bool SPHERE>
+__device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r, int jseg, SegOut& out,
+                                            unsigned& evals) {
+  out.valid = 0;
+  const float ta = T.tau[jseg], tb = T.tau[jseg + 1];
+  const float ua = t_to_u(r, ta);
+  const float ub = fminf(t_to_u(r, tb), r.uexit);
+  const int m = T.m0[jseg];
+  const int S = 1 << m;
+  // top level: walk the level-m texels crossed for u in [ua, ub]
+  int cx = (r.i >> m) + (int)floorf(ldexpf((float)(r.i & (S - 1)) + 0.5f + r.Kx * ua, -m));
+  int cy = (r.j >> m) + (int)floorf(ldexpf((float)(r.j & (S - 1)) + 0.5f + r.Ky * ua, -m));
+  float best = SS_INF, bu0 = ua, bu1 = ua;
+  int bx = cx, by = cy, have = 0;
+  float u0 = ua;
+  for (int it = 0; it < 8; ++it) {
+    const float ux = r.sx > 0 ? ((float)(((cx + 1) << m) - r.i) - 0.5f) * r.invKx
+                   : (r.sx < 0 ? ((float)((cx << m) - r.i) - 0.5f) * r.invKx : SS_INF);
+    const float uy = r.sy > 0 ? ((float)(((cy + 1) << m) - r.j) - 0.5f) * r.invKy
+                   : (r.sy < 0 ? ((float)((cy << m) - r.j) - 0.5f) * r.invKy : SS_INF);
+    const float u1 = fminf(fminf(ux, uy), ub);
+    if (u1 > u0) {
+      const float lb = lower_bound(r, T, m, cx, cy, u0, u1);
+      evals++;
+      if (lb <= best) {
+        best = lb;
+        bx = cx;
+        by = cy;
+        bu0 = u0;
+        bu1 = u1;
+        have = 1;
+      }
+      u0 = u1;
+    }
+    if (!(u1 < ub)) break;
+    const bool stepx = ux <= uy, stepy = uy <= ux;
+    if (stepx) cx += r.sx;
+    if (stepy) cy += r.sy;
+  }
+  if (!have) return;
+  // descend: the children of the chosen texel crossed by the ray, split at the
+  // parent's two mid-lines (at most three pieces)
+  for (int lv = m; lv > 0; --lv) {
+    const int half = 1 << (lv - 1);
+    const float mxr = (float)((2 * bx + 1) * half - r.i) - 0.5f;
+    const float myr = (float)((2 * by + 1) * half - r.j) - 0.5f;
+    const float umx = r.sx ? mxr * r.invKx : SS_INF;
+    const float umy = r.sy ? myr * r.invKy : SS_INF;
+    const float c1 = fminf(fmaxf(fminf(umx, umy), bu0), bu1);
+    const float c2 = fminf(fmaxf(fmaxf(umx, umy), bu0), bu1);
+    const float pa[3] = {bu0, c1, c2};
+    const float pb[3] = {c1, c2, bu1};
+    float nbest = SS_INF, n0 = bu0, n1 = bu1;
+    int nx = 2 * bx, ny = 2 * by;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float u = pa[k], v = pb[k];
+      const float um = 0.5f * (u + v);
+      const int ccx = 2 * bx + ((r.Kx * um >= mxr) ? 1 : 0);
+      const int ccy = 2 * by + ((r.Ky * um >= myr) ? 1 : 0);
+      const float lb = lower_bound(r, T, lv - 1, ccx, ccy, u, v);
+      const bool ok = v > u;
+      evals += ok ? 1u : 0u;
+      if (ok && lb <= nbest) {
+        nbest = lb;
+        nx = ccx;
+        ny = ccy;
+        n0 = u;
+        n1 = v;
+      }
+    }
+    bx = nx;
+    by = ny;
+    bu0 = n0;
+    bu1 = n1;
+  }
+  // final samples on the half-texel grid t_n = (n + 1) delta/2 around the
+  // middle of the base texel's stretch of ray
+  const float tin = u_to_t(r, bu0), tout = u_to_t(r, bu1);
+  const float tmid = 0.5f * (tin + tout);
+  const int nc = (int)floorf((tmid - T.half_delta) * T.two_over_delta + 0.5f);
+  float bdh = SS_INF, bt = 0.0f, bu = 0.0f;
+  int found = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int n = nc - 1 + k;
+    const float t = (float)(n + 1) * T.half_delta;
+    const float u = t_to_u(r, t);
+    if (n >= 0 && u < r.uexit) {
+      const Sample s = sample_at(r, T, t, u);
+      evals++;
+      if (s.dh <= bdh) {
+        bdh = s.dh;
+        bt = t;
+        bu = u;
+        found = 1;
+      }
+    }
+  }
+  if (!found) return;
+  out.alpha = clearance(r, bt, bdh);
+  out.t = bt;
+  out.u = bu;
+  out.valid = 1;
+}
+
+// Lower bound of the clearance of every sample at ray length >= t when no
+// terrain rises above `top` (relative to h_p, >= 0): the clearance of the
+// point at that height below the tip grows with t on the plane and the
+// sphere.  Used for result-invariant early exits.
+template <bool SPHERE>
+__device__ __forceinline__ float clearance_floor(const Ray<SPHERE>& r, const TileK& T, float t, float top) {
+  const float d = tip_rise(r, T, t) - top;
+  return d > 0.0f ? clearance(r, t, d) : -SS_INF;
+}
+
+struct RayResult {
+  float alpha;
+  float t, u;
+  int valid;
+};
+
+// Smallest clearance over the concatenated runs (Sec. 3.3).
+template <bool SPHERE>
+__device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>& r, float top,
+                                               unsigned& evals) {
+  RayResult res;
+  res.alpha = SS_INF;
+  res.t = 0.0f;
+  res.u = 0.0f;
+  res.valid = 0;
+  for (int j = 0; j < T.nseg; ++j) {
+    const float ta = T.tau[j];
+    if (!(t_to_u(r, ta) < r.uexit)) break;  // the run starts outside the tile
+    if (T.prune) {
+      const float tlo = fmaxf(T.half_delta, ta - 1.5f * T.half_delta);
+      if (clearance_floor(r, T, tlo, top) >= fminf(res.alpha, T.rL) + T.prune_margin) break;
+    }
+    SegOut so;
+    descend_run(T, r, j, so, evals);
+    if (so.valid && so.alpha < res.alpha) {
+      res.alpha = so.alpha;
+      res.t = so.t;
+      res.u = so.u;
+      res.valid = 1;
+    }
+    if (T.prune && res.alpha <= -T.rL) break;  // umbra: nothing can change s = 0
+  }
+  return res;
+}
+
+// Uniform stepping (Sec. 2, Fig. 1b): every step, smallest clearance.  The
+// running minimum is kept as a tangent ratio; atan is taken once.
+template <bool SPHERE>
+__device__ __forceinline__ float shadow_uniform(const TileK& T, const Ray<SPHERE>& r, float top,
+                                                unsigned& evals) {
+  float best = SS_INF;  // tangent of the smallest clearance among samples with D > 0
+  int anyneg = 0;       // a sample with D <= 0 and N < 0 (clearance below -pi/2)
+  float t = T.half_delta;
+  for (int k = 0; k < (1 << 22); ++k, t = T.half_delta + (float)k * T.ustep) {
+    if (t > T.ucap) break;
+    const float u = t_to_u(r, t);
+    if (!(u < r.uexit)) break;
+    if (T.prune && (k & 15) == 0) {
+      const float cur = anyneg ? -SS_INF : (best < SS_INF ? atanf(best) : SS_INF);
+      if (cur <= -T.rL) break;
+      if (clearance_floor(r, T, t, top) >= fminf(cur, T.rL) + T.prune_margin) break;
+    }
+    const Sample s = sample_at(r, T, t, u);
+    evals++;
+    float num, den;
+    if (SPHERE) {
+      const float x = t * r.invrho;
+      const float w = ss_sqrt(1.0f + x * (2.0f * r.sp + x));
+      num = s.dh * r.cp;
+      den = t * w - s.dh * (r.sp + x);
+    } else {
+      num = s.dh * r.cp;
+      den = t - s.dh * r.sp;
+    }
+    if (den > 0.0f) {
+      best = fminf(best, num * ss_rcp(den));
+    } else if (num < 0.0f) {
+      anyneg = 1;
+    }
+  }
+  if (anyneg) return -SS_INF;
+  return best < SS_INF ? atanf(best) : SS_INF;
+}

@@ -1,0 +1,282 @@
+// Shadow-factor kernels for gfx950: forward (descent or uniform stepping),
+// its instrumented twin, and the adjoint.
+//
+// One lane = one ray (texel centre); one wavefront = a TW x TH ray tile; a
+// 256-thread workgroup = 2 x 2 wavefront tiles.  Workgroup ids are remapped
+// so each XCD (ids are dealt round-robin over the 8 XCDs) works on one
+// contiguous band of the tile and its rays reuse that XCD's L2.
+#include "kernels.h"
+#include "ray.h"
+
+namespace ss {
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+  return x * per + min(x, rem) + k;
+}
+
+__device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int TW>
+__device__ __forceinline__ void ray_coords(int nbx, int nblocks, int& i, int& j) {
+  constexpr int TH = 64 / TW;
+  const int b = xcd_remap((int)blockIdx.x, nblocks);
+  const int bxi = b % nbx, byi = b / nbx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  i = bxi * (2 * TW) + (wave & 1) * TW + lane % TW;
+  j = byi * (2 * TH) + (wave >> 1) * TH + lane / TW;
+}
+
+template <bool SPHERE, int TW, int MODE, bool COUNT>
+__global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict__ out,
+                                                     unsigned long long* counter, int nbx,
+                                                     int nblocks) {
+  int i, j;
+  ray_coords<TW>(nbx, nblocks, i, j);
+  unsigned evals = 0;
+  if (i < T.W && j < T.H) {
+    const float hp = T.h[j * T.W + i];
+    Ray<SPHERE> r;
+    ray_init(T, i, j, hp, r);
+    const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
+    float alpha;
+    if (MODE == SS_MODE_DP)
+      alpha = shadow_dp(T, r, top, evals).alpha;
+    else
+      alpha = shadow_uniform(T, r, top, evals);
+    out[j * T.W + i] = disc_fraction(alpha, T);
+  }
+  if (COUNT) {
+    const unsigned s = wave_sum_u32(evals);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(counter, (unsigned long long)s);
+  }
+}
+
+// Adjoint: recompute the forward decisions, then the chain rule through the
+// deciding sample (see the derivation in DESIGN.md, "Adjoint").
+struct SunTrig {
+  float se, ce, sa, ca, tan_e;
+};
+
+template <bool SPHERE, int TW>
+__global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
+                                                      const float* __restrict__ gs,
+                                                      float* __restrict__ gh,
+                                                      double* __restrict__ gsun, int nbx,
+                                                      int nblocks) {
+  int i, j;
+  ray_coords<TW>(nbx, nblocks, i, j);
+  double ge = 0.0, ga = 0.0;
+  if (i < T.W && j < T.H) {
+    const float g = gs[j * T.W + i];
+    const float hp = T.h[j * T.W + i];
+    Ray<SPHERE> r;
+    ray_init(T, i, j, hp, r);
+    const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
+    unsigned evals = 0;
+    const RayResult res = shadow_dp(T, r, top, evals);
+    const float dd = res.alpha * T.inv_rL;
+    if (res.valid && g != 0.0f && fabsf(dd) < 1.0f) {
+      const float t = res.t, u = res.u;
+      const Sample s = sample_at(r, T, t, u);
+      const float dh = s.dh;
+      const float galpha = g * 2.0f * sqrtf(1.0f - dd * dd) * (0.318309886183791f * T.inv_rL);
+      float num, den, x = 0.0f, w = 1.0f;
+      if (SPHERE) {
+        x = t * r.invrho;
+        w = sqrtf(1.0f + x * (2.0f * r.sp + x));
+        num = dh * r.cp;
+        den = t * w - dh * (r.sp + x);
+      } else {
+        num = dh * r.cp;
+        den = t - dh * r.sp;
+      }
+      const float inv2 = 1.0f / (num * num + den * den);
+      const float a_n = galpha * den * inv2;
+      const float a_d = -galpha * num * inv2;
+      float a_dh, a_cp, a_sp, a_t, a_hp = 0.0f;
+      float a_Lx = 0.0f, a_Ly = 0.0f, a_Lz = 0.0f;
+      // bilinear taps
+      const int xa = min(max(s.x0, 0), T.W - 1), xb = min(max(s.x0 + 1, 0), T.W - 1);
+      const int ya = min(max(s.y0, 0), T.H - 1), yb = min(max(s.y0 + 1, 0), T.H - 1);
+      const float h00 = T.h[ya * T.W + xa], h10 = T.h[ya * T.W + xb];
+      const float h01 = T.h[yb * T.W + xa], h11 = T.h[yb * T.W + xb];
+      const float gxh = (1.0f - s.fy) * (h10 - h00) + s.fy * (h11 - h01);
+      const float gyh = (1.0f - s.fx) * (h01 - h00) + s.fx * (h11 - h10);
+      if (SPHERE) {
+        const float X = ((float)i + 0.5f - 0.5f * (float)T.W) * T.texel;
+        const float Y = ((float)j + 0.5f - 0.5f * (float)T.H) * T.texel;
+        const float aa = X * T.invR, bb = Y * T.invR;
+        const float gg = sqrtf(1.0f + aa * aa + bb * bb);
+        const float r1 = 1.0f + hp * T.invR;
+        const float G = gg / (r1 * T.texel);
+        a_dh = a_n * r.cp - a_d * (r.sp + x);
+        a_cp = a_n * dh;
+        a_t = a_d * w;
+        float a_w = a_d * t;
+        a_sp = -a_d * dh;
+        float a_x = -a_d * dh;
+        // dh = dH(t, rho, sp) - (hb - hp)
+        const float a_hb = -a_dh;
+        a_hp += a_dh;
+        const float spx = r.sp + x;
+        const float wm1 = x * (2.0f * r.sp + x) / (w + 1.0f);
+        a_t += a_dh * spx / w;
+        a_sp += a_dh * t / w;
+        float a_rho = a_dh * (wm1 - x * spx / w);
+        a_x += a_w * spx / w;
+        a_sp += a_w * x / w;
+        a_t += a_x * r.invrho;
+        a_rho -= a_x * x * r.invrho;
+        // texture position d = K u(t)
+        const float a_dx = a_hb * gxh, a_dy = a_hb * gyh;
+        const float omc = 1.0f - r.c * u;  // = 1 / (1 + c t)
+        const float k1 = omc * omc;
+        const float aK = a_dx * r.Kx + a_dy * r.Ky;
+        a_t += aK * k1;
+        a_rho -= aK * k1 * x;
+        a_Lx += a_dx * G * u;
+        a_Ly += a_dy * G * u;
+        a_Lz += -G * u * (a_dx * aa + a_dy * bb) - aK * k1 * t * t * (gg * T.invR / r1);
+        // s_p = (aa Lx + bb Ly + Lz)/g and c_p = sqrt(1 - s_p^2)
+        a_sp += -a_cp * r.sp / r.cp;
+        const float ig = 1.0f / gg;
+        a_Lx += a_sp * aa * ig;
+        a_Ly += a_sp * bb * ig;
+        a_Lz += a_sp * ig;
+        a_hp += a_rho;
+        // taps
+        atomicAdd(&gh[ya * T.W + xa], a_hb * (1.0f - s.fx) * (1.0f - s.fy));
+        atomicAdd(&gh[ya * T.W + xb], a_hb * s.fx * (1.0f - s.fy));
+        atomicAdd(&gh[yb * T.W + xa], a_hb * (1.0f - s.fx) * s.fy);
+        atomicAdd(&gh[yb * T.W + xb], a_hb * s.fx * s.fy);
+      } else {
+        a_dh = a_n * r.cp - a_d * r.sp;
+        a_cp = a_n * dh;
+        a_sp = -a_d * dh;
+        a_t = a_d;
+        a_t += a_dh * T.Lz;
+        a_Lz += a_dh * t;
+        const float a_hb = -a_dh;
+        a_hp += a_dh;
+        const float a_dx = a_hb * gxh, a_dy = a_hb * gyh;
+        const float it = 1.0f / T.texel;
+        a_t += (a_dx * T.Lx + a_dy * T.Ly) * it;
+        a_Lx += a_dx * t * it;
+        a_Ly += a_dy * t * it;
+        a_Lz += a_sp;
+        if (r.cp > 0.0f) {
+          a_Lx += a_cp * T.Lx / r.cp;
+          a_Ly += a_cp * T.Ly / r.cp;
+        }
+        atomicAdd(&gh[ya * T.W + xa], a_hb * (1.0f - s.fx) * (1.0f - s.fy));
+        atomicAdd(&gh[ya * T.W + xb], a_hb * s.fx * (1.0f - s.fy));
+        atomicAdd(&gh[yb * T.W + xa], a_hb * (1.0f - s.fx) * s.fy);
+        atomicAdd(&gh[yb * T.W + xb], a_hb * s.fx * s.fy);
+      }
+      atomicAdd(&gh[j * T.W + i], a_hp);
+      // t = (n + 1) texel / (2 cos e) grows with e; L(e, a) on the unit sphere
+      const double dte = (double)a_t * (double)t * (double)st.tan_e;
+      ge = dte + (double)a_Lx * (-(double)st.se * st.ca) + (double)a_Ly * (-(double)st.se * st.sa) +
+           (double)a_Lz * (double)st.ce;
+      ga = (double)a_Lx * (-(double)st.ce * st.sa) + (double)a_Ly * ((double)st.ce * st.ca);
+    }
+  }
+  ge = wave_sum_f64(ge);
+  ga = wave_sum_f64(ga);
+  if ((threadIdx.x & 63) == 0 && (ge != 0.0 || ga != 0.0)) {
+    atomicAdd(&gsun[0], ge);
+    atomicAdd(&gsun[1], ga);
+  }
+}
+
+static int tile_width_of(int code) {
+  switch (code) {
+    case SS_TILE_16x4: return 16;
+    case SS_TILE_4x16: return 4;
+    case SS_TILE_32x2: return 32;
+    default: return 8;
+  }
+}
+
+void grid_for(const TileK& T, int ray_tile, int* nbx, int* nblocks) {
+  const int tw = tile_width_of(ray_tile), th = 64 / tw;
+  const int bx = (T.W + 2 * tw - 1) / (2 * tw);
+  const int by = (T.H + 2 * th - 1) / (2 * th);
+  *nbx = bx;
+  *nblocks = bx * by;
+}
+
+template <bool SPHERE, int TW>
+static hipError_t launch_fwd_tw(const TileK& T, int mode, bool count, float* out,
+                                unsigned long long* counter, hipStream_t stream) {
+  int nbx, nb;
+  grid_for(T, TW == 16 ? SS_TILE_16x4 : TW == 4 ? SS_TILE_4x16 : TW == 32 ? SS_TILE_32x2 : SS_TILE_8x8,
+           &nbx, &nb);
+  if (nb == 0) return hipSuccess;
+  dim3 grid(nb), block(256);
+  if (mode == SS_MODE_DP) {
+    if (count)
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_DP, true>), grid, block, 0, stream, T,
+                         out, counter, nbx, nb);
+    else
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_DP, false>), grid, block, 0, stream, T,
+                         out, counter, nbx, nb);
+  } else {
+    if (count)
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_UNIFORM, true>), grid, block, 0, stream,
+                         T, out, counter, nbx, nb);
+    else
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_UNIFORM, false>), grid, block, 0,
+                         stream, T, out, counter, nbx, nb);
+  }
+  return hipGetLastError();
+}
+
+template <bool SPHERE>
+static hipError_t launch_fwd_s(const TileK& T, int mode, int ray_tile, bool count, float* out,
+                               unsigned long long* counter, hipStream_t stream) {
+  switch (ray_tile) {
+    case SS_TILE_16x4: return launch_fwd_tw<SPHERE, 16>(T, mode, count, out, counter, stream);
+    case SS_TILE_4x16: return launch_fwd_tw<SPHERE, 4>(T, mode, count, out, counter, stream);
+    case SS_TILE_32x2: return launch_fwd_tw<SPHERE, 32>(T, mode, count, out, counter, stream);
+    default: return launch_fwd_tw<SPHERE, 8>(T, mode, count, out, counter, stream);
+  }
+}
+
+hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, bool count,
+                          float* out, unsigned long long* counter, hipStream_t stream) {
+  return sphere ? launch_fwd_s<true>(T, mode, ray_tile, count, out, counter, stream)
+                : launch_fwd_s<false>(T, mode, ray_tile, count, out, counter, stream);
+}
+
+hipError_t launch_adjoint(const TileK& T, bool sphere, double elev, double azim, const float* gs,
+                          float* gh, double* gsun, hipStream_t stream) {
+  SunTrig st;
+  st.se = (float)sin(elev);
+  st.ce = (float)cos(elev);
+  st.sa = (float)sin(azim);
+  st.ca = (float)cos(azim);
+  st.tan_e = (float)tan(elev);
+  int nbx, nb;
+  grid_for(T, SS_TILE_8x8, &nbx, &nb);
+  if (nb == 0) return hipSuccess;
+  dim3 grid(nb), block(256);
+  if (sphere)
+    hipLaunchKernelGGL((adjoint_kernel<true, 8>), grid, block, 0, stream, T, st, gs, gh, gsun, nbx, nb);
+  else
+    hipLaunchKernelGGL((adjoint_kernel<false, 8>), grid, block, 0, stream, T, st, gs, gh, gsun, nbx, nb);
+  return hipGetLastError();
+}
+
+}  // namespace ss

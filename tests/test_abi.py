@@ -1,0 +1,142 @@
+"""Host-only checks of the C ABI: the library loads without a GPU, exports
+every symbol include/softshadow.h declares, computes the mipmap layout, and
+rejects bad arguments before anything is enqueued (no device call is made)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2005_06671_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "softshadow.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ss_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L.lib(), n), n
+    assert set(names) == set(L.SIGNATURES)
+
+
+def test_layout(L):
+    lib = L.lib()
+    assert lib.ss_maxmip_levels(256, 256) == 9
+    assert lib.ss_maxmip_levels(16384, 16384) == 15
+    assert lib.ss_maxmip_levels(1, 1) == 1
+    assert lib.ss_maxmip_levels(0, 5) == 0
+    assert lib.ss_maxmip_floats(1, 1) == 0
+    for W, H in [(256, 256), (1536, 1536), (37, 53), (4096, 2048)]:
+        nl = lib.ss_maxmip_levels(W, H)
+        prev = 0
+        w, h = W, H
+        for m in range(1, nl):
+            off = lib.ss_maxmip_level_offset(W, H, m)
+            assert off % 64 == 0 and off >= prev
+            w, h = (w + 1) // 2, (h + 1) // 2
+            prev = off + w * h
+        assert lib.ss_maxmip_floats(W, H) >= prev
+    assert lib.ss_maxmip_level_offset(256, 256, 0) == -1
+    assert lib.ss_maxmip_level_offset(256, 256, 10) == -1
+    assert lib.ss_maxmip_floats(-1, 4) == -1
+
+
+def good(L):
+    fake = 0x100000
+    t = L.SSTile(fake, fake, 64, 64, 10.0)
+    s = L.SSSun(math.radians(1.5), 0.3, math.radians(0.267))
+    p = L.SSParams(1737400.0, 0.0, 5, 0, 0, 0, 1.0, 1, 0)
+    return t, s, p
+
+
+def cast(L, t, s, p, out=0x200000):
+    return L.lib().ss_shadow_cast(C.byref(t), C.byref(s), C.byref(p), out, None)
+
+
+def test_rejects_bad_arguments(L):
+    lib = L.lib()
+    t, s, p = good(L)
+    assert lib.ss_shadow_cast(None, C.byref(s), C.byref(p), 0x200000, None) == L.SS_ERR_INVALID_ARG
+    for field, val in [("width", -3), ("texel_m", 0.0), ("texel_m", float("nan"))]:
+        t2, _, _ = good(L)
+        setattr(t2, field, val)
+        assert cast(L, t2, s, p) == L.SS_ERR_INVALID_ARG, field
+    t2, _, _ = good(L)
+    t2.height = 0
+    assert cast(L, t2, s, p) == L.SS_ERR_INVALID_ARG
+    t2, _, _ = good(L)
+    t2.maxmip = 0
+    assert cast(L, t2, s, p) == L.SS_ERR_INVALID_ARG
+    for field, val in [("elev_rad", math.pi / 2), ("ang_radius_rad", 0.0), ("azim_rad", math.inf)]:
+        _, s2, _ = good(L)
+        setattr(s2, field, val)
+        assert cast(L, t, s2, p) == L.SS_ERR_INVALID_ARG, field
+    for field, val in [("body_radius_m", -1.0), ("mode", 7), ("schedule", 3), ("prune", 2),
+                       ("ray_tile", 9), ("n_segments", -1), ("uniform_step", -1.0)]:
+        _, _, p2 = good(L)
+        setattr(p2, field, val)
+        assert cast(L, t, s, p2) == L.SS_ERR_INVALID_ARG, field
+    assert cast(L, t, s, p, out=0) == L.SS_ERR_INVALID_ARG
+    # a schedule with more runs than supported
+    _, _, p2 = good(L)
+    p2.schedule = 1
+    p2.n_prime0 = 1
+    p2.max_len_m = 1e6
+    assert cast(L, t, s, p2) == L.SS_ERR_UNSUPPORTED
+    # backward needs the descent
+    _, _, p3 = good(L)
+    p3.mode = 1
+    assert lib.ss_shadow_cast_backward(C.byref(t), C.byref(s), C.byref(p3), 0x300000, 0x400000,
+                                       0x500000, None) == L.SS_ERR_UNSUPPORTED
+    assert lib.ss_shadow_cast_counted(C.byref(t), C.byref(s), C.byref(p), 0x200000, None,
+                                      None) == L.SS_ERR_INVALID_ARG
+
+
+def test_batched_validation(L):
+    lib = L.lib()
+    t, s, p = good(L)
+    tiles = (L.SSTile * 2)(t, t)
+    suns = (L.SSSun * 3)(s, s, s)
+    outs = (C.c_void_p * 6)(*([0x600000] * 6))
+    need = lib.ss_batched_workspace_bytes(2, 3)
+    assert need > 0 and lib.ss_batched_workspace_bytes(-1, 3) == -1
+    assert lib.ss_shadow_cast_batched(tiles, 2, suns, 3, C.byref(p), outs, 0x700000, need - 1,
+                                      None) == L.SS_ERR_WORKSPACE
+    assert lib.ss_shadow_cast_batched(tiles, 2, suns, 3, C.byref(p), outs, 0x700001, need,
+                                      None) == L.SS_ERR_WORKSPACE
+    outs[4] = None
+    assert lib.ss_shadow_cast_batched(tiles, 2, suns, 3, C.byref(p), outs, 0x700000, need,
+                                      None) == L.SS_ERR_INVALID_ARG
+    assert lib.ss_shadow_cast_batched(tiles, 0, suns, 3, C.byref(p), outs, 0, 0, None) == 0
+    plan = C.c_void_p()
+    assert lib.ss_batched_plan_create(tiles, 2, suns, 3, C.byref(p), outs, 0x700000, need, None,
+                                      None) == L.SS_ERR_INVALID_ARG
+    assert lib.ss_batched_plan_launch(None, None) == L.SS_ERR_INVALID_ARG
+    assert lib.ss_batched_plan_destroy(None) == 0
+
+
+def test_status_strings(L):
+    lib = L.lib()
+    for code in (0, -1, -2, -3, -4, -99):
+        assert isinstance(lib.ss_status_string(code), bytes)
+
+
+def test_product_fails_loudly_without_library(monkeypatch):
+    from paper_2005_06671_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libsoftshadow.so")
+    with pytest.raises(ImportError):
+        _lib.lib()

@@ -172,7 +172,7 @@ def test_tie_enumeration_reduces_to_plain_path(orc, shape, D, radius):
     p = orc.Params(W, rows, D, radius, math.radians(1.0), 2.2, RL)
     _, alpha = orc.shadow(h, p)
     for lin in range(0, W * rows, 7):
-        alts = orc.alternatives(h, p, lin, 0.0, 0.0, 0.0)
+        alts = orc.alternatives(h, p, lin, 0.0, 0.0, 0.0, 0.0)
         assert alts is not None and len(alts) == 1
         assert alts[0] == alpha.flat[lin] or (np.isinf(alts[0]) and np.isinf(alpha.flat[lin]))
 
@@ -182,7 +182,7 @@ def test_tie_enumeration_contains_plain_path(orc):
     p = orc.Params(48, 48, 10.0, R, math.radians(1.0), 2.2, RL)
     _, alpha = orc.shadow(h, p)
     for lin in range(0, 48 * 48, 5):
-        alts = orc.alternatives(h, p, lin, 1e-2, 1e-2, 1e-3)
+        alts = orc.alternatives(h, p, lin, 1e-2, 1e-7, 1e-3, 1e-6)
         assert alts is not None
         a = alpha.flat[lin]
         assert np.any(alts == a) or (np.isinf(a) and np.any(np.isinf(alts)))
