@@ -1,0 +1,261 @@
+#!/usr/bin/env python
+"""Benchmark of the soft-shadow hot path on one MI355X.
+
+Workload (the 4096^2 tile configuration): a 4096 x 4096 fp32 DEM at 5 m/texel
+(seeded fBm, 2 km amplitude, plus 2000 power-law craters) on a sphere of radius
+1737.4 km, 8 seeded suns with elevation uniform in [0.5, 3] degrees and disc
+radius 0.267 degrees, shadow rays capped at 30 km of horizontal travel.
+
+One step = build the maximum mipmap + run the descent forward for all 8 suns
+(8 x 16.8 M rays).  `value` is rays per second of the whole step, inputs
+resident in HBM.  Beside it the JSON line reports uniform stepping on the same
+suns (the paper's baseline), forward+backward throughput, the roofline of the
+dominant kernel, and the FP64 CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s DP+max-mip vs uniform stepping (fwd, fwd+bwd) at |Δ|≤1e-4 on 1 GPU"
+WORKLOAD = ("tile: 4096x4096 fp32 DEM, 5 m/texel, fBm 2 km + 2000 craters, sphere R=1737.4 km, "
+            "8 suns elev U[0.5,3] deg, r_L=0.267 deg, 30 km rays")
+
+# Algorithmic VALU work per unit, in issue slots of one lane (full-rate FP32 /
+# INT32 op = 1; v_rcp / v_sqrt = 4, they issue at quarter rate), counted from
+# the formulas each unit evaluates.
+OPS_LB = 51       # one max-mip lower bound: piece split, child index, t(u), tip rise, fetch, argmin
+OPS_SAMPLE = 64   # one bilinear clearance sample of the descent (t_n, u, taps, tip rise, argmin)
+OPS_RAY = 200     # per ray: origin frame, exit, per-run clearance angle, disc fraction
+OPS_USTEP = 76    # one uniform step: sample + clearance tangent + running min
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz VALU lane-slots (FP32 not packed)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+DP_SOURCES = ["paper_2005_06671_amd/csrc/ray.h", "paper_2005_06671_amd/csrc/shadow.hip",
+              "paper_2005_06671_amd/csrc/common.h"]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the descent kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "shadow_dp_tile_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_src_sha") != src_hash(DP_SOURCES):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(h_np, params_or, seconds=15.0):
+    """The FP64 oracle on a bounded random sample of the workload's rays."""
+    import numpy as np
+    import oracle
+    threads = max(1, len(os.sched_getaffinity(0)))
+    rng = np.random.default_rng(1234)
+    n_all = h_np.size
+    oracle.shadow(h_np, params_or, np.arange(1, dtype=np.int64))  # builds the oracle's mipmap
+    # grow the sample until it takes about `seconds` of wall time
+    n = 4096 * threads
+    while True:
+        rays = rng.choice(n_all, size=min(n_all, n), replace=False)
+        t0 = time.perf_counter()
+        oracle.shadow_threaded(h_np, params_or, rays, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.6 * seconds or rays.size >= n_all:
+            break
+        n = int(rays.size * min(8.0, max(1.5, seconds / max(dt, 1e-3))))
+    n = rays.size
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} random texels of the 4096^2 tile, first sun, descent, FP64 C oracle on "
+                      f"{threads} host threads ({cpu}), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip uniform and backward legs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 512 MiB device copy first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the path would "
+              "shard by replicating the DEM and its mipmap and splitting ray blocks across GPUs, "
+              "which this single-GPU build does not implement", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2005_06671_amd as ss
+    from synth import config, dem_for, sun_list, seed_of, R_MOON
+
+    dev = torch.device("cuda:0")
+    c = config("tile")
+    W, H, D = c["tiles"][0]
+    suns = sun_list("tile")
+    h = dem_for("tile", device=dev)
+    mm = torch.empty(ss.maxmip_floats(W, H), dtype=torch.float32, device=dev)
+    outs = [torch.empty_like(h) for _ in suns]
+    params = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"])
+    rays_per_step = W * H * len(suns)
+    stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy:
+        a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def pair():
+        return (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    # events for every launch of the timed region, read after it ends
+    ev_dp = [[pair() for _ in suns] for _ in range(args.steps)]
+    ev_mm = [pair() for _ in range(args.steps)]
+
+    def step(i=None):
+        if i is not None:
+            ev_mm[i][0].record(stream)
+        ss.maxmip(h, out=mm)
+        if i is not None:
+            ev_mm[i][1].record(stream)
+        for k, (e, a, r) in enumerate(suns):
+            if i is not None:
+                ev_dp[i][k][0].record(stream)
+            ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
+            if i is not None:
+                ev_dp[i][k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / max(1, args.steps)
+    value = rays_per_step / (ms_per_step / 1e3) / 1e6
+    launch_ms = [a.elapsed_time(b) for row in ev_dp for a, b in row]
+    maxmip_ms = [a.elapsed_time(b) for a, b in ev_mm]
+    avg_dp_ms = float(np.mean(launch_ms))
+    avg_mm_ms = float(np.mean(maxmip_ms))
+
+    # algorithmic units per launch (instrumented twin of the same kernel, untimed)
+    units = []
+    for k, (e, a, r) in enumerate(suns):
+        _, cnt = ss.shadow_cast_counted(h, D, e, a, r, params, mm=mm)
+        units.append([int(x) for x in cnt.cpu().tolist()])
+    n_lb = float(np.mean([u[0] for u in units]))
+    n_smp = float(np.mean([u[1] for u in units]))
+    ops_per_launch = OPS_LB * n_lb + OPS_SAMPLE * n_smp + OPS_RAY * W * H
+    achieved = ops_per_launch / (avg_dp_ms / 1e3) / 1e12
+    traffic = traffic_from_profile()
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic,
+                "kernel": "shadow_kernel<sphere, 8x8, descent>",
+                "avg_launch_ms": avg_dp_ms, "lb_evals_per_ray": n_lb / (W * H),
+                "samples_per_ray": n_smp / (W * H),
+                "ops_model": {"lb": OPS_LB, "sample": OPS_SAMPLE, "ray": OPS_RAY}}
+    mm_bytes = 4.0 * W * H + 4.0 * sum(
+        ((W + (1 << m) - 1) >> m) * ((H + (1 << m) - 1) >> m) for m in range(1, ss.maxmip_levels(W, H)))
+    maxmip = {"bound": "hbm", "avg_launch_ms": avg_mm_ms,
+              "achieved_GBs": mm_bytes / (avg_mm_ms / 1e3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
+              "frac": mm_bytes / (avg_mm_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
+              "note": "64 MiB source is L2/MALL resident between steps (warm)"}
+
+    extras = {}
+    if not args.no_extras:
+        # uniform stepping, one texel per step, same suns, cap and exits
+        pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
+        for k, (e, a, r) in enumerate(suns[:1]):
+            ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=outs[k])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ss.maxmip(h, out=mm)
+        for k, (e, a, r) in enumerate(suns):
+            ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=outs[k])
+        torch.cuda.synchronize()
+        tu = time.perf_counter() - t0
+        uniform = rays_per_step / tu / 1e6
+        extras["uniform_mrays_s"] = uniform
+        extras["speedup_vs_uniform"] = value / uniform
+        ucnt = []
+        for k, (e, a, r) in enumerate(suns[:2]):
+            _, cnt = ss.shadow_cast_counted(h, D, e, a, r, pu, mm=mm)
+            ucnt.append(int(cnt[1].item()))
+        extras["uniform_steps_per_ray"] = float(np.mean(ucnt)) / (W * H)
+        # forward + backward (hand-written adjoint) for every sun
+        g = torch.randn(H, W, generator=torch.Generator(device="cpu").manual_seed(7)).to(dev)
+        gh = torch.zeros_like(h)
+        gsun = torch.zeros(2, dtype=torch.float64, device=dev)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ss.maxmip(h, out=mm)
+            for k, (e, a, r) in enumerate(suns):
+                ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
+                ss.shadow_cast_backward(h, D, e, a, g, r, params, mm=mm, grad_h=gh, grad_sun=gsun)
+            torch.cuda.synchronize()
+            tfb = time.perf_counter() - t0
+        extras["fwd_bwd_mrays_s"] = rays_per_step / tfb / 1e6
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        e, a, r = suns[0]
+        po = oracle.Params(W, H, D, R_MOON, e, a, r, max_len_m=c["max_len"])
+        cpu = cpu_baseline(h.cpu().numpy(), po)
+
+    line = {"metric": METRIC, "value": value, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": WORKLOAD, "rays_per_step": rays_per_step, "suns": len(suns),
+                       "seed": seed_of("tile"), "mode": "descent (geometric runs from N'=5)"},
+            "roofline": roofline, "cpu_baseline": cpu, "maxmip": maxmip}
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -105,8 +105,9 @@ int32_t ss_maxmip_build(const float* d_height, int32_t width, int32_t rows, floa
 int32_t ss_shadow_cast(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                        float* d_shadow, void* stream);
 
-/* Instrumented variant: same output, and adds the number of lower-bound
- * evaluations plus final samples (uniform: steps) to *d_eval_count. */
+/* Instrumented variant: same output; adds the number of max-mip lower-bound
+ * evaluations to d_eval_count[0] and of bilinear clearance samples (the
+ * descent's final samples, or uniform steps) to d_eval_count[1]. */
 int32_t ss_shadow_cast_counted(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                                float* d_shadow, unsigned long long* d_eval_count, void* stream);
 

@@ -3,7 +3,7 @@
  * TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the bench's CPU
  * baseline use it; the product path never does.  Every function below follows
  * the paper passage named in its comment.  Where the paper is silent or
- * garbled the reading is stated in the comment and listed in the design doc.
+ * garbled, the reading taken is stated in the comment.
  *
  * Pins (tests/test_oracle_*.py): maximum mipmap against a direct block-max
  * definition and its invariants; geometry against closed forms (gnomonic round

@@ -113,14 +113,14 @@ def shadow_cast(h: torch.Tensor, texel_m: float, elev: float, azim: float,
 
 def shadow_cast_counted(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=None, mm=None,
                         out=None):
-    """(s, number of lower-bound evaluations + final samples) of one forward launch."""
+    """(s, [lower-bound evaluations, bilinear samples]) of one forward launch."""
     _dev_f32_2d(h)
     params = params or Params()
     if mm is None:
         mm = maxmip(h)
     if out is None:
         out = torch.empty_like(h)
-    cnt = torch.zeros(1, dtype=torch.int64, device=h.device)
+    cnt = torch.zeros(2, dtype=torch.int64, device=h.device)
     t = _tile(h, mm, texel_m)
     s = _sun(elev, azim, ang_radius)
     p = params.c()

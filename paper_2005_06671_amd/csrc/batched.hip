@@ -55,12 +55,12 @@ __global__ __launch_bounds__(256) void batched_kernel(const TileK* __restrict__ 
         Ray<SPHERE> r;
         ray_init(T, i, j, hp, r);
         const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
-        unsigned evals = 0;
+        unsigned n_lb = 0, n_smp = 0;
         float alpha;
         if (MODE == SS_MODE_DP)
-          alpha = shadow_dp(T, r, top, evals).alpha;
+          alpha = shadow_dp(T, r, top, n_lb, n_smp).alpha;
         else
-          alpha = shadow_uniform(T, r, top, evals);
+          alpha = shadow_uniform(T, r, top, n_smp);
         out[j * T.W + i] = disc_fraction(alpha, T);
       }
     }

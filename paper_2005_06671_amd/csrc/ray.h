@@ -189,7 +189,7 @@ struct SegOut {
 // texel apart around the chosen base texel (Alg. 1, final level).
 template <bool SPHERE>
 __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r, int jseg, SegOut& out,
-                                            unsigned& evals) {
+                                            unsigned& n_lb, unsigned& n_smp) {
   out.valid = 0;
   const float ta = T.tau[jseg], tb = T.tau[jseg + 1];
   const float ua = t_to_u(r, ta);
@@ -210,7 +210,7 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     const float u1 = fminf(fminf(ux, uy), ub);
     if (u1 > u0) {
       const float lb = lower_bound(r, T, m, cx, cy, u0, u1);
-      evals++;
+      n_lb++;
       if (lb <= best) {
         best = lb;
         bx = cx;
@@ -249,7 +249,7 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
       const int ccy = 2 * by + ((r.Ky * um >= myr) ? 1 : 0);
       const float lb = lower_bound(r, T, lv - 1, ccx, ccy, u, v);
       const bool ok = v > u;
-      evals += ok ? 1u : 0u;
+      n_lb += ok ? 1u : 0u;
       if (ok && lb <= nbest) {
         nbest = lb;
         nx = ccx;
@@ -277,7 +277,7 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     const float u = t_to_u(r, t);
     if (n >= 0 && u < r.uexit) {
       const Sample s = sample_at(r, T, t, u);
-      evals++;
+      n_smp++;
       if (s.dh <= bdh) {
         bdh = s.dh;
         bt = t;
@@ -312,7 +312,7 @@ struct RayResult {
 // Smallest clearance over the concatenated runs (Sec. 3.3).
 template <bool SPHERE>
 __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>& r, float top,
-                                               unsigned& evals) {
+                                               unsigned& n_lb, unsigned& n_smp) {
   RayResult res;
   res.alpha = SS_INF;
   res.t = 0.0f;
@@ -326,7 +326,7 @@ __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>
       if (clearance_floor(r, T, tlo, top) >= fminf(res.alpha, T.rL) + T.prune_margin) break;
     }
     SegOut so;
-    descend_run(T, r, j, so, evals);
+    descend_run(T, r, j, so, n_lb, n_smp);
     if (so.valid && so.alpha < res.alpha) {
       res.alpha = so.alpha;
       res.t = so.t;
@@ -342,7 +342,7 @@ __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>
 // running minimum is kept as a tangent ratio; atan is taken once.
 template <bool SPHERE>
 __device__ __forceinline__ float shadow_uniform(const TileK& T, const Ray<SPHERE>& r, float top,
-                                                unsigned& evals) {
+                                                unsigned& n_smp) {
   float best = SS_INF;  // tangent of the smallest clearance among samples with D > 0
   int anyneg = 0;       // a sample with D <= 0 and N < 0 (clearance below -pi/2)
   float t = T.half_delta;
@@ -356,7 +356,7 @@ __device__ __forceinline__ float shadow_uniform(const TileK& T, const Ray<SPHERE
       if (clearance_floor(r, T, t, top) >= fminf(cur, T.rL) + T.prune_margin) break;
     }
     const Sample s = sample_at(r, T, t, u);
-    evals++;
+    n_smp++;
     float num, den;
     if (SPHERE) {
       const float x = t * r.invrho;

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
                                                      int nblocks) {
   int i, j;
   ray_coords<TW>(nbx, nblocks, i, j);
-  unsigned evals = 0;
+  unsigned n_lb = 0, n_smp = 0;
   if (i < T.W && j < T.H) {
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
@@ -51,19 +51,26 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
     const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
     float alpha;
     if (MODE == SS_MODE_DP)
-      alpha = shadow_dp(T, r, top, evals).alpha;
+      alpha = shadow_dp(T, r, top, n_lb, n_smp).alpha;
     else
-      alpha = shadow_uniform(T, r, top, evals);
+      alpha = shadow_uniform(T, r, top, n_smp);
     out[j * T.W + i] = disc_fraction(alpha, T);
   }
   if (COUNT) {
-    const unsigned s = wave_sum_u32(evals);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(counter, (unsigned long long)s);
+    const unsigned a = wave_sum_u32(n_lb), b = wave_sum_u32(n_smp);
+    if ((threadIdx.x & 63) == 0) {
+      if (a) atomicAdd(&counter[0], (unsigned long long)a);
+      if (b) atomicAdd(&counter[1], (unsigned long long)b);
+    }
   }
 }
 
-// Adjoint: recompute the forward decisions, then the chain rule through the
-// deciding sample (see the derivation in DESIGN.md, "Adjoint").
+// Adjoint: recompute the forward decisions, then apply the chain rule through
+// the deciding sample.  With the decisions fixed, s depends on the origin
+// height (through rho and the texture path), the four bilinear taps, and the
+// sun direction (through L, s_p, c_p, the texture path and t* = (n*+1) delta/2
+// with delta = texel / cos e).  Each partial below is the derivative of the
+// forward expression it sits next to.
 struct SunTrig {
   float se, ce, sa, ca, tan_e;
 };
@@ -83,8 +90,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
     const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
-    unsigned evals = 0;
-    const RayResult res = shadow_dp(T, r, top, evals);
+    unsigned n_lb = 0, n_smp = 0;
+    const RayResult res = shadow_dp(T, r, top, n_lb, n_smp);
     const float dd = res.alpha * T.inv_rL;
     if (res.valid && g != 0.0f && fabsf(dd) < 1.0f) {
       const float t = res.t, u = res.u;

@@ -2,8 +2,9 @@
 
 These stand in for the lunar polar DEMs the paper renders (Sec. 3.1 quotes
 30 m/texel LOLA-class data; Sec. 6.3 uses stitched fields of 1024-2048 texels).
-The recipe (octaves, persistence, amplitude, crater count, diameter law, bowl
-depth, rim height) is stated in the design doc's input section.
+The recipe: 8 octaves of gradient noise with persistence 0.5 and lacunarity 2
+over the tile extent, plus bowl craters (depth 0.2 D, rim 0.04 D) whose
+diameters follow a cumulative D^-2 law on [50 m, 5 km].
 
 Everything runs in torch float64 on the requested device and is rounded to
 float32 at the end.  The same seed gives the same array on the same device.

@@ -19,7 +19,10 @@ import oracle
 
 TOL = 1e-4
 # FP32 resolution of the kernels' decisions: heights eh_abs + eh_rel * t (m),
-# positions et_abs + et_rel * (t / delta) (texels); see the design doc.
+# positions et_abs + et_rel * (t / delta) (texels).  An FP32 lower bound or
+# clearance carries a few ulps of the tip rise (<= ~2.5 km) plus the position
+# error times the slope; positions carry ~3e-7 relative error of the offset
+# from the origin (K u), i.e. ~1e-6 texel per texel travelled with margin.
 EH = (4e-3, 2e-7)
 ET = (2e-3, 1e-6)
 
