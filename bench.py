@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip uniform and backward legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration)")
+    ap.add_argument("--dem-cache", default="",
+                    help="load the DEM from this .npy if present, else generate and save it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the path would "
@@ -132,7 +134,12 @@ def main():
     c = config("tile")
     W, H, D = c["tiles"][0]
     suns = sun_list("tile")
-    h = dem_for("tile", device=dev)
+    if args.dem_cache and os.path.exists(args.dem_cache):
+        h = torch.from_numpy(np.load(args.dem_cache)).to(dev)
+    else:
+        h = dem_for("tile", device=dev)
+        if args.dem_cache:
+            np.save(args.dem_cache, h.cpu().numpy())
     mm = torch.empty(ss.maxmip_floats(W, H), dtype=torch.float32, device=dev)
     outs = [torch.empty_like(h) for _ in suns]
     params = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"])

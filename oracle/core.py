@@ -41,7 +41,8 @@ TRACE_DTYPE = np.dtype([("seg", np.int32), ("n", np.int32), ("t", np.float64),
                         ("dh", np.float64), ("alpha", np.float64), ("base_i", np.int32),
                         ("base_j", np.int32), ("evals", np.int32), ("margin_lb", np.float64),
                         ("margin_dh", np.float64), ("margin_round", np.float64),
-                        ("margin_seg", np.float64), ("margin_geo", np.float64)], align=True)
+                        ("margin_seg", np.float64), ("margin_geo", np.float64),
+                        ("margin_tap", np.float64)], align=True)
 
 
 def load():

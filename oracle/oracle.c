@@ -352,9 +352,19 @@ int or_cells_on_path(const ray_t* r, int m, double ta, double tb, const cand_t* 
   ev[ne++] = tb;
   qsort(ev + 1, (size_t)(ne - 2), sizeof(double), cmp_double);
   if (min_gap) {
+    /* spacing of the real decisions: crossings inside (ta, tb) and the ends.
+     * A crossing that coincides with an end to rounding is the parent's own
+     * boundary line seen again one level down, not a decision. */
+    double tiny = 1e-9 * (fabs(ta) + fabs(tb) + r->s->delta);
+    double prev = ta;
     for (int k = 1; k < ne; ++k) {
-      double g = (ev[k] - ev[k - 1]) / r->s->delta;
+      int is_end = (k == ne - 1);
+      if (!is_end && (ev[k] - ta <= tiny || tb - ev[k] <= tiny)) continue;
+      /* in texels, relative to the texels travelled (FP32 position error grows
+       * with the offset from the origin) */
+      double g = (ev[k] - prev) / (r->s->delta + ev[k]);
       if (g < *min_gap) *min_gap = g;
+      prev = ev[k];
     }
   }
   int n = 0;
@@ -504,6 +514,16 @@ static double shadow_dp(const ray_t* r, or_trace* tr) {
   }
   t0.alpha = alpha;
   t0.margin_seg = second - alpha;
+  t0.margin_tap = INFINITY;
+  if (t0.n >= 0) {
+    /* the bilinear height is continuous across the lines through texel
+     * centres, its slope is not */
+    double qx, qy, Hd;
+    or_ray_point(r, t0.t, &qx, &qy, &Hd);
+    double fx = qx - 0.5 - floor(qx - 0.5), fy = qy - 0.5 - floor(qy - 0.5);
+    double m = fmin(fmin(fx, 1.0 - fx), fmin(fy, 1.0 - fy));
+    t0.margin_tap = m / (1.0 + t0.t / s->delta);
+  }
   if (tr) *tr = t0;
   return alpha;
 }
@@ -538,6 +558,7 @@ static double shadow_uniform(const ray_t* r, or_trace* tr) {
     }
   }
   t0.alpha = alpha;
+  t0.margin_tap = INFINITY;
   if (tr) *tr = t0;
   return alpha;
 }

@@ -154,7 +154,7 @@ static int32_t check_sun(const ss_sun* s) {
   if (!s) return SS_ERR_INVALID_ARG;
   if (!(fabs(s->elev_rad) < 0.5 * M_PI)) return SS_ERR_INVALID_ARG;
   if (!isfinite(s->azim_rad)) return SS_ERR_INVALID_ARG;
-  if (!(s->ang_radius_rad > 0.0) || !isfinite(s->ang_radius_rad)) return SS_ERR_INVALID_ARG;
+  if (!(s->ang_radius_rad > 0.0) || !(s->ang_radius_rad < 0.5)) return SS_ERR_INVALID_ARG;
   return SS_OK;
 }
 
@@ -187,6 +187,8 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
   K->rL = (float)s->ang_radius_rad;
   K->inv_rL = (float)(1.0 / s->ang_radius_rad);
   K->prune_margin = 1e-5f;
+  K->tan_rL = (float)tan(s->ang_radius_rad);
+  K->tan_margin = (float)tan(1e-5);
   K->prune = rp.prune;
   K->ustep = (float)(rp.uniform_step * delta);
 

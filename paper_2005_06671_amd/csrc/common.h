@@ -23,6 +23,8 @@ struct TileK {
   float two_over_delta;      // 2 / delta
   float rL, inv_rL;          // sun disc angular radius and its inverse
   float prune_margin;        // safety margin (rad) of the result-invariant exits
+  float tan_rL;              // tan(r_L)
+  float tan_margin;          // tan(prune_margin)
   float ustep;               // uniform stepping: step in ray length (m)
   float ucap;                // uniform stepping: cap on ray length (m), +inf = tile edge
   int nseg;                  // number of concatenated runs

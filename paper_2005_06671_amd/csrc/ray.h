@@ -109,11 +109,14 @@ __device__ __forceinline__ const float* level_ptr(const TileK& T, int m) {
   return m == 0 ? T.h : T.mm + T.loff[m];
 }
 
+// Keeps an index inside [0, n): a negative index wraps to a huge unsigned
+// value and lands on n - 1.  Only rounding at a tile edge can produce an index
+// outside the level, so this is a memory-safety guard, not a behaviour.
+__device__ __forceinline__ unsigned inside(int v, int n) { return min((unsigned)v, (unsigned)(n - 1)); }
+
 __device__ __forceinline__ float mip_at(const TileK& T, int m, int cx, int cy) {
-  const int w = T.lw[m], hgt = T.lh[m];
-  cx = min(max(cx, 0), w - 1);
-  cy = min(max(cy, 0), hgt - 1);
-  return level_ptr(T, m)[cy * w + cx];
+  const unsigned w = (unsigned)T.lw[m];
+  return level_ptr(T, m)[inside(cy, T.lh[m]) * w + inside(cx, T.lw[m])];
 }
 
 // Lower bound of the clearance over the part [u0, u1] of the ray inside a
@@ -125,6 +128,13 @@ __device__ __forceinline__ float lower_bound(const Ray<SPHERE>& r, const TileK& 
   const float uc = fminf(fmaxf(r.uhmin, u0), u1);
   const float t = u_to_t(r, uc);
   return tip_rise(r, T, t) - (mip_at(T, m, cx, cy) - r.hp);
+}
+
+// The same bound when the tip rise at the texel's entry is already known (the
+// tip height rises from the start, so the entry is where it is smallest).
+__device__ __forceinline__ float lower_bound_at(const TileK& T, float rise, int m, int cx, int cy,
+                                                float hp) {
+  return rise - (mip_at(T, m, cx, cy) - hp);
 }
 
 // Bilinear sample of the terrain below the ray tip at ray length t (u = u(t)):
@@ -144,27 +154,17 @@ __device__ __forceinline__ Sample sample_at(const Ray<SPHERE>& r, const TileK& T
   s.fy = dy - fly;
   s.x0 = r.i + (int)flx;
   s.y0 = r.j + (int)fly;
-  const int x0 = min(max(s.x0, 0), T.W - 1), x1 = min(max(s.x0 + 1, 0), T.W - 1);
-  const int y0 = min(max(s.y0, 0), T.H - 1), y1 = min(max(s.y0 + 1, 0), T.H - 1);
+  // clamp to the edge (the tap index is -1 only left of the first centre)
+  const unsigned x0 = (unsigned)min(max(s.x0, 0), T.W - 1), x1 = inside(s.x0 + 1, T.W);
+  const unsigned y0 = (unsigned)min(max(s.y0, 0), T.H - 1), y1 = inside(s.y0 + 1, T.H);
   const float* h = T.h;
-  const float h00 = h[y0 * T.W + x0] - r.hp, h10 = h[y0 * T.W + x1] - r.hp;
-  const float h01 = h[y1 * T.W + x0] - r.hp, h11 = h[y1 * T.W + x1] - r.hp;
+  const unsigned W = (unsigned)T.W;
+  const float h00 = h[y0 * W + x0] - r.hp, h10 = h[y0 * W + x1] - r.hp;
+  const float h01 = h[y1 * W + x0] - r.hp, h11 = h[y1 * W + x1] - r.hp;
   const float hb = (1.0f - s.fy) * ((1.0f - s.fx) * h00 + s.fx * h10) +
                    s.fy * ((1.0f - s.fx) * h01 + s.fx * h11);
   s.dh = tip_rise(r, T, t) - hb;
   return s;
-}
-
-// Signed angle at p between L and the terrain point below the ray tip
-// (positive: below the ray).  First order: (dh / t) |n x L| (Sec. 3.4, Eq. 5).
-template <bool SPHERE>
-__device__ __forceinline__ float clearance(const Ray<SPHERE>& r, float t, float dh) {
-  if (SPHERE) {
-    const float x = t * r.invrho;
-    const float w = ss_sqrt(1.0f + x * (2.0f * r.sp + x));
-    return atan2f(dh * r.cp, t * w - dh * (r.sp + x));
-  }
-  return atan2f(dh * r.cp, t - dh * r.sp);
 }
 
 // Visible part of the sun disc above a chord at d disc radii below its centre
@@ -176,12 +176,35 @@ __device__ __forceinline__ float disc_fraction(float alpha, const TileK& T) {
          0.318309886183791f;
 }
 
+// Clearance of a sample: the signed angle at p between L and the terrain point
+// below the ray tip (positive: below the ray), atan2(num, den) with the terms
+// below; to first order (dh / t) |n x L| (Sec. 3.4, Eq. 5).  Runs are compared by the
+// tangent key num/den (den > 0; +inf / -inf when the angle is beyond +-pi/2),
+// which orders like the angle, so atan runs once per ray.
 struct SegOut {
-  float alpha;
+  float key;
   float t;        // ray length of the deciding sample
   float u;
   int valid;
 };
+
+template <bool SPHERE>
+__device__ __forceinline__ void clearance_terms(const Ray<SPHERE>& r, float t, float dh, float& num,
+                                                float& den) {
+  if (SPHERE) {
+    const float x = t * r.invrho;
+    const float w = ss_sqrt(1.0f + x * (2.0f * r.sp + x));
+    num = dh * r.cp;
+    den = t * w - dh * (r.sp + x);
+  } else {
+    num = dh * r.cp;
+    den = t - dh * r.sp;
+  }
+}
+
+__device__ __forceinline__ float tangent_key(float num, float den) {
+  return den > 0.0f ? num * ss_rcp(den) : (num >= 0.0f ? SS_INF : -SS_INF);
+}
 
 // One concatenated run (Sec. 3.3): descent from level m0 = T.m0[j] over the
 // texels the ray crosses (Sec. 3.2, Fig. 3b), strict argmin from the far end
@@ -199,17 +222,22 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   // top level: walk the level-m texels crossed for u in [ua, ub]
   int cx = (r.i >> m) + (int)floorf(ldexpf((float)(r.i & (S - 1)) + 0.5f + r.Kx * ua, -m));
   int cy = (r.j >> m) + (int)floorf(ldexpf((float)(r.j & (S - 1)) + 0.5f + r.Ky * ua, -m));
-  float best = SS_INF, bu0 = ua, bu1 = ua;
+  float best = SS_INF, bu0 = ua, bu1 = ua, brise = 0.0f;
   int bx = cx, by = cy, have = 0;
   float u0 = ua;
+  const bool rising = r.uhmin <= ua;  // tip height grows over the whole run
   for (int it = 0; it < 8; ++it) {
     const float ux = r.sx > 0 ? ((float)(((cx + 1) << m) - r.i) - 0.5f) * r.invKx
                    : (r.sx < 0 ? ((float)((cx << m) - r.i) - 0.5f) * r.invKx : SS_INF);
     const float uy = r.sy > 0 ? ((float)(((cy + 1) << m) - r.j) - 0.5f) * r.invKy
                    : (r.sy < 0 ? ((float)((cy << m) - r.j) - 0.5f) * r.invKy : SS_INF);
     const float u1 = fminf(fminf(ux, uy), ub);
-    if (u1 > u0) {
-      const float lb = lower_bound(r, T, m, cx, cy, u0, u1);
+    // a piece in a texel outside the level is a rounding sliver at the tile edge
+    const bool in_level = (unsigned)cx < (unsigned)T.lw[m] && (unsigned)cy < (unsigned)T.lh[m];
+    if (u1 > u0 && in_level) {
+      const float uc = fminf(fmaxf(r.uhmin, u0), u1);
+      const float rise = tip_rise(r, T, u_to_t(r, uc));
+      const float lb = lower_bound_at(T, rise, m, cx, cy, r.hp);
       n_lb++;
       if (lb <= best) {
         best = lb;
@@ -217,10 +245,11 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
         by = cy;
         bu0 = u0;
         bu1 = u1;
+        brise = rise;
         have = 1;
       }
-      u0 = u1;
     }
+    if (u1 > u0) u0 = u1;
     if (!(u1 < ub)) break;
     const bool stepx = ux <= uy, stepy = uy <= ux;
     if (stepx) cx += r.sx;
@@ -239,16 +268,29 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     const float c2 = fminf(fmaxf(fmaxf(umx, umy), bu0), bu1);
     const float pa[3] = {bu0, c1, c2};
     const float pb[3] = {c1, c2, bu1};
-    float nbest = SS_INF, n0 = bu0, n1 = bu1;
-    int nx = 2 * bx, ny = 2 * by;
+    // tip rise at each piece's entry: the first piece enters where the parent
+    // did (already known); identical to evaluating it again
+    float rise[3];
+    if (rising) {
+      rise[0] = brise;
+      rise[1] = tip_rise(r, T, u_to_t(r, c1));
+      rise[2] = tip_rise(r, T, u_to_t(r, c2));
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        rise[k] = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, pa[k]), pb[k])));
+    }
+    float nbest = SS_INF, n0 = bu0, n1 = bu1, nrise = brise;
+    int nx = 2 * bx, ny = 2 * by, nh = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float u = pa[k], v = pb[k];
       const float um = 0.5f * (u + v);
       const int ccx = 2 * bx + ((r.Kx * um >= mxr) ? 1 : 0);
       const int ccy = 2 * by + ((r.Ky * um >= myr) ? 1 : 0);
-      const float lb = lower_bound(r, T, lv - 1, ccx, ccy, u, v);
-      const bool ok = v > u;
+      const float lb = lower_bound_at(T, rise[k], lv - 1, ccx, ccy, r.hp);
+      // children beyond a ragged edge are absent
+      const bool ok = v > u && ccx < T.lw[lv - 1] && ccy < T.lh[lv - 1];
       n_lb += ok ? 1u : 0u;
       if (ok && lb <= nbest) {
         nbest = lb;
@@ -256,12 +298,16 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
         ny = ccy;
         n0 = u;
         n1 = v;
+        nrise = rise[k];
+        nh = 1;
       }
     }
+    if (!nh) return;
     bx = nx;
     by = ny;
     bu0 = n0;
     bu1 = n1;
+    brise = nrise;
   }
   // final samples on the half-texel grid t_n = (n + 1) delta/2 around the
   // middle of the base texel's stretch of ray
@@ -287,20 +333,62 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     }
   }
   if (!found) return;
-  out.alpha = clearance(r, bt, bdh);
+  float num, den;
+  clearance_terms(r, bt, bdh, num, den);
+  out.key = tangent_key(num, den);
   out.t = bt;
   out.u = bu;
   out.valid = 1;
 }
 
-// Lower bound of the clearance of every sample at ray length >= t when no
-// terrain rises above `top` (relative to h_p, >= 0): the clearance of the
-// point at that height below the tip grows with t on the plane and the
-// sphere.  Used for result-invariant early exits.
+// True when every sample at ray length >= t clears the angle whose tangent is
+// need_tan (an angle in (-pi/2, pi/2)), given that no terrain rises above
+// `top` (relative to h_p, >= 0): the clearance of the point at that height
+// below the tip grows with t on the plane and on the sphere.  Used for the
+// result-invariant early exits.
 template <bool SPHERE>
-__device__ __forceinline__ float clearance_floor(const Ray<SPHERE>& r, const TileK& T, float t, float top) {
+__device__ __forceinline__ bool clears(const Ray<SPHERE>& r, const TileK& T, float t, float top,
+                                       float need_tan) {
   const float d = tip_rise(r, T, t) - top;
-  return d > 0.0f ? clearance(r, t, d) : -SS_INF;
+  if (!(d > 0.0f)) return false;
+  float num, den;
+  clearance_terms(r, t, d, num, den);
+  return den <= 0.0f || num >= need_tan * den;  // den <= 0: at least pi/2
+}
+
+// tan(min(alpha, r_L) + margin) for the tangent key of alpha (tan addition).
+__device__ __forceinline__ float need_tangent(const TileK& T, float key) {
+  const float k = fmaxf(fminf(key, T.tan_rL), -1e30f);
+  return (k + T.tan_margin) * ss_rcp(1.0f - k * T.tan_margin);
+}
+
+// Highest terrain (relative to h_p, at least 0) that any bilinear tap of run
+// j's final samples can touch: the samples lie on the ray for t in
+// [tlo, tau_{j+1} + 3 delta/4] inside the tile, and a sample at texture point q
+// reads taps within [q - 3/2, q + 1/2] per axis.  That box spans at most two
+// texels per axis of level max(m0 + 1, 3), whose maxima bound it.
+template <bool SPHERE>
+__device__ __forceinline__ float run_top(const TileK& T, const Ray<SPHERE>& r, int j, float tlo) {
+  const int mb = max(T.m0[j] + 1, 3);
+  if (mb >= T.L) return fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp;
+  const float ulo = t_to_u(r, tlo);
+  const float uhi = fminf(t_to_u(r, T.tau[j + 1] + 1.5f * T.half_delta), r.uexit);
+  const float xa = r.Kx * ulo, xb = r.Kx * uhi, ya = r.Ky * ulo, yb = r.Ky * uhi;
+  // FP32 slack on the offsets (relative ~1e-6) plus a hundredth of a texel
+  const float sx = 0.01f + 1e-5f * fmaxf(fabsf(xa), fabsf(xb));
+  const float sy = 0.01f + 1e-5f * fmaxf(fabsf(ya), fabsf(yb));
+  const float x0 = (float)r.i + 0.5f + fminf(xa, xb) - 1.5f - sx;
+  const float x1 = (float)r.i + 0.5f + fmaxf(xa, xb) + 0.5f + sx;
+  const float y0 = (float)r.j + 0.5f + fminf(ya, yb) - 1.5f - sy;
+  const float y1 = (float)r.j + 0.5f + fmaxf(ya, yb) + 0.5f + sy;
+  const int ix0 = min(max((int)floorf(x0), 0), T.W - 1) >> mb;
+  const int ix1 = min(max((int)floorf(x1), 0), T.W - 1) >> mb;
+  const int iy0 = min(max((int)floorf(y0), 0), T.H - 1) >> mb;
+  const int iy1 = min(max((int)floorf(y1), 0), T.H - 1) >> mb;
+  if (ix1 > ix0 + 1 || iy1 > iy0 + 1) return fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp;
+  const float m = fmaxf(fmaxf(mip_at(T, mb, ix0, iy0), mip_at(T, mb, ix1, iy0)),
+                        fmaxf(mip_at(T, mb, ix0, iy1), mip_at(T, mb, ix1, iy1)));
+  return fmaxf(m, r.hp) - r.hp;
 }
 
 struct RayResult {
@@ -309,70 +397,64 @@ struct RayResult {
   int valid;
 };
 
+__device__ __forceinline__ float angle_of(float key) {
+  return key == SS_INF ? SS_INF : (key == -SS_INF ? -SS_INF : atanf(key));
+}
+
 // Smallest clearance over the concatenated runs (Sec. 3.3).
 template <bool SPHERE>
 __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>& r, float top,
                                                unsigned& n_lb, unsigned& n_smp) {
   RayResult res;
-  res.alpha = SS_INF;
   res.t = 0.0f;
   res.u = 0.0f;
   res.valid = 0;
+  float best = SS_INF;                    // tangent key of the smallest clearance so far
+  float need = need_tangent(T, SS_INF);   // tan(min(alpha, r_L) + margin)
   for (int j = 0; j < T.nseg; ++j) {
     const float ta = T.tau[j];
     if (!(t_to_u(r, ta) < r.uexit)) break;  // the run starts outside the tile
     if (T.prune) {
+      // every final sample of run j lies at t >= tau_j - 3 delta/4
       const float tlo = fmaxf(T.half_delta, ta - 1.5f * T.half_delta);
-      if (clearance_floor(r, T, tlo, top) >= fminf(res.alpha, T.rL) + T.prune_margin) break;
+      if (clears(r, T, tlo, top, need)) break;                     // nothing ahead is high enough
+      if (clears(r, T, tlo, run_top(T, r, j, tlo), need)) continue;  // nor in this run
     }
     SegOut so;
     descend_run(T, r, j, so, n_lb, n_smp);
-    if (so.valid && so.alpha < res.alpha) {
-      res.alpha = so.alpha;
+    if (so.valid && so.key < best) {
+      best = so.key;
       res.t = so.t;
       res.u = so.u;
       res.valid = 1;
+      need = need_tangent(T, best);
     }
-    if (T.prune && res.alpha <= -T.rL) break;  // umbra: nothing can change s = 0
+    if (T.prune && best <= -T.tan_rL) break;  // umbra: nothing can change s = 0
   }
+  res.alpha = angle_of(best);
   return res;
 }
 
-// Uniform stepping (Sec. 2, Fig. 1b): every step, smallest clearance.  The
-// running minimum is kept as a tangent ratio; atan is taken once.
+// Uniform stepping (Sec. 2, Fig. 1b): every step, smallest clearance, kept as
+// a tangent key; atan is taken once.
 template <bool SPHERE>
 __device__ __forceinline__ float shadow_uniform(const TileK& T, const Ray<SPHERE>& r, float top,
                                                 unsigned& n_smp) {
-  float best = SS_INF;  // tangent of the smallest clearance among samples with D > 0
-  int anyneg = 0;       // a sample with D <= 0 and N < 0 (clearance below -pi/2)
+  float best = SS_INF;
   float t = T.half_delta;
   for (int k = 0; k < (1 << 22); ++k, t = T.half_delta + (float)k * T.ustep) {
     if (t > T.ucap) break;
     const float u = t_to_u(r, t);
     if (!(u < r.uexit)) break;
     if (T.prune && (k & 15) == 0) {
-      const float cur = anyneg ? -SS_INF : (best < SS_INF ? atanf(best) : SS_INF);
-      if (cur <= -T.rL) break;
-      if (clearance_floor(r, T, t, top) >= fminf(cur, T.rL) + T.prune_margin) break;
+      if (best <= -T.tan_rL) break;
+      if (clears(r, T, t, top, need_tangent(T, best))) break;
     }
     const Sample s = sample_at(r, T, t, u);
     n_smp++;
     float num, den;
-    if (SPHERE) {
-      const float x = t * r.invrho;
-      const float w = ss_sqrt(1.0f + x * (2.0f * r.sp + x));
-      num = s.dh * r.cp;
-      den = t * w - s.dh * (r.sp + x);
-    } else {
-      num = s.dh * r.cp;
-      den = t - s.dh * r.sp;
-    }
-    if (den > 0.0f) {
-      best = fminf(best, num * ss_rcp(den));
-    } else if (num < 0.0f) {
-      anyneg = 1;
-    }
+    clearance_terms(r, t, s.dh, num, den);
+    best = fminf(best, tangent_key(num, den));
   }
-  if (anyneg) return -SS_INF;
-  return best < SS_INF ? atanf(best) : SS_INF;
+  return angle_of(best);
 }
