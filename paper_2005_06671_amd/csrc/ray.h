@@ -73,8 +73,10 @@ __device__ __forceinline__ void ray_init(const TileK& T, int i, int j, float hp,
   }
   r.sx = r.Kx > 0.0f ? 1 : (r.Kx < 0.0f ? -1 : 0);
   r.sy = r.Ky > 0.0f ? 1 : (r.Ky < 0.0f ? -1 : 0);
-  r.invKx = r.sx ? 1.0f / r.Kx : 0.0f;
-  r.invKy = r.sy ? 1.0f / r.Ky : 0.0f;
+  // +inf on an axis the path never moves along: every crossing time on it is
+  // then +-inf (the numerators are half-integers, never 0)
+  r.invKx = r.sx ? 1.0f / r.Kx : SS_INF;
+  r.invKy = r.sy ? 1.0f / r.Ky : SS_INF;
   // leaving the tile: first boundary in the direction of travel
   float ux = SS_INF, uy = SS_INF;
   if (r.sx > 0) ux = ((float)(T.W - i) - 0.5f) / r.Kx;
@@ -117,6 +119,26 @@ __device__ __forceinline__ unsigned inside(int v, int n) { return min((unsigned)
 __device__ __forceinline__ float mip_at(const TileK& T, int m, int cx, int cy) {
   const unsigned w = (unsigned)T.lw[m];
   return level_ptr(T, m)[inside(cy, T.lh[m]) * w + inside(cx, T.lw[m])];
+}
+
+// One mip level as a buffer resource: 32-bit offsets, and an offset past the
+// end reads 0 instead of faulting (the hardware range check), so gathers for
+// candidates that are then discarded need no clamping.
+struct Level {
+  __amdgpu_buffer_rsrc_t rs;
+  int w;
+};
+
+__device__ __forceinline__ Level level_of(const TileK& T, int m) {
+  Level L;
+  L.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(level_ptr(T, m)), 0,
+                                           T.lw[m] * T.lh[m] * 4, 0x00020000);
+  L.w = T.lw[m];
+  return L;
+}
+
+__device__ __forceinline__ float level_at(const Level& L, int cx, int cy) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(L.rs, (cy * L.w + cx) * 4, 0, 0));
 }
 
 // Lower bound of the clearance over the part [u0, u1] of the ray inside a
@@ -219,95 +241,92 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   const float ub = fminf(t_to_u(r, tb), r.uexit);
   const int m = T.m0[jseg];
   const int S = 1 << m;
+  const bool rising = r.uhmin <= ua;  // tip height grows over the whole run
+  // the next grid line ahead of the current texel on each axis (+1 when the
+  // path moves forward or not at all)
+  const int ex = r.Kx >= 0.0f ? 1 : 0, ey = r.Ky >= 0.0f ? 1 : 0;
   // top level: walk the level-m texels crossed for u in [ua, ub]
   int cx = (r.i >> m) + (int)floorf(ldexpf((float)(r.i & (S - 1)) + 0.5f + r.Kx * ua, -m));
   int cy = (r.j >> m) + (int)floorf(ldexpf((float)(r.j & (S - 1)) + 0.5f + r.Ky * ua, -m));
+  const Level Ltop = level_of(T, m);
   float best = SS_INF, bu0 = ua, bu1 = ua, brise = 0.0f;
   int bx = cx, by = cy, have = 0;
   float u0 = ua;
-  const bool rising = r.uhmin <= ua;  // tip height grows over the whole run
   for (int it = 0; it < 8; ++it) {
-    const float ux = r.sx > 0 ? ((float)(((cx + 1) << m) - r.i) - 0.5f) * r.invKx
-                   : (r.sx < 0 ? ((float)((cx << m) - r.i) - 0.5f) * r.invKx : SS_INF);
-    const float uy = r.sy > 0 ? ((float)(((cy + 1) << m) - r.j) - 0.5f) * r.invKy
-                   : (r.sy < 0 ? ((float)((cy << m) - r.j) - 0.5f) * r.invKy : SS_INF);
+    const float ux = ((float)(((cx + ex) << m) - r.i) - 0.5f) * r.invKx;
+    const float uy = ((float)(((cy + ey) << m) - r.j) - 0.5f) * r.invKy;
     const float u1 = fminf(fminf(ux, uy), ub);
     // a piece in a texel outside the level is a rounding sliver at the tile edge
-    const bool in_level = (unsigned)cx < (unsigned)T.lw[m] && (unsigned)cy < (unsigned)T.lh[m];
-    if (u1 > u0 && in_level) {
-      const float uc = fminf(fmaxf(r.uhmin, u0), u1);
-      const float rise = tip_rise(r, T, u_to_t(r, uc));
-      const float lb = lower_bound_at(T, rise, m, cx, cy, r.hp);
-      n_lb++;
-      if (lb <= best) {
-        best = lb;
-        bx = cx;
-        by = cy;
-        bu0 = u0;
-        bu1 = u1;
-        brise = rise;
-        have = 1;
-      }
-    }
-    if (u1 > u0) u0 = u1;
+    const bool ok = u1 > u0 && (unsigned)cx < (unsigned)T.lw[m] && (unsigned)cy < (unsigned)T.lh[m];
+    const float uc = fminf(fmaxf(r.uhmin, u0), u1);
+    const float rise = tip_rise(r, T, u_to_t(r, uc));
+    const float lb = rise - (level_at(Ltop, cx, cy) - r.hp);
+    n_lb += ok ? 1u : 0u;
+    const bool take = ok && lb <= best;
+    best = take ? lb : best;
+    bx = take ? cx : bx;
+    by = take ? cy : by;
+    bu0 = take ? u0 : bu0;
+    bu1 = take ? u1 : bu1;
+    brise = take ? rise : brise;
+    have |= take ? 1 : 0;
+    u0 = fmaxf(u0, u1);
     if (!(u1 < ub)) break;
-    const bool stepx = ux <= uy, stepy = uy <= ux;
-    if (stepx) cx += r.sx;
-    if (stepy) cy += r.sy;
+    cx += ux <= uy ? r.sx : 0;
+    cy += uy <= ux ? r.sy : 0;
   }
   if (!have) return;
   // descend: the children of the chosen texel crossed by the ray, split at the
-  // parent's two mid-lines (at most three pieces)
+  // parent's two mid-lines into at most three pieces
   for (int lv = m; lv > 0; --lv) {
     const int half = 1 << (lv - 1);
-    const float mxr = (float)((2 * bx + 1) * half - r.i) - 0.5f;
-    const float myr = (float)((2 * by + 1) * half - r.j) - 0.5f;
-    const float umx = r.sx ? mxr * r.invKx : SS_INF;
-    const float umy = r.sy ? myr * r.invKy : SS_INF;
+    const Level Lc = level_of(T, lv - 1);
+    const int px = 2 * bx, py = 2 * by;
+    const float mxr = (float)((px + 1) * half - r.i) - 0.5f;
+    const float myr = (float)((py + 1) * half - r.j) - 0.5f;
+    const float umx = mxr * r.invKx, umy = myr * r.invKy;
     const float c1 = fminf(fmaxf(fminf(umx, umy), bu0), bu1);
     const float c2 = fminf(fmaxf(fmaxf(umx, umy), bu0), bu1);
-    const float pa[3] = {bu0, c1, c2};
-    const float pb[3] = {c1, c2, bu1};
+    // child texel of each piece from its midpoint
+    const float m0 = 0.5f * (bu0 + c1), m1 = 0.5f * (c1 + c2), m2 = 0.5f * (c2 + bu1);
+    const int x0 = px + (r.Kx * m0 >= mxr ? 1 : 0), y0 = py + (r.Ky * m0 >= myr ? 1 : 0);
+    const int x1 = px + (r.Kx * m1 >= mxr ? 1 : 0), y1 = py + (r.Ky * m1 >= myr ? 1 : 0);
+    const int x2 = px + (r.Kx * m2 >= mxr ? 1 : 0), y2 = py + (r.Ky * m2 >= myr ? 1 : 0);
+    const float M0 = level_at(Lc, x0, y0), M1 = level_at(Lc, x1, y1), M2 = level_at(Lc, x2, y2);
     // tip rise at each piece's entry: the first piece enters where the parent
     // did (already known); identical to evaluating it again
-    float rise[3];
+    float r0, r1, r2;
     if (rising) {
-      rise[0] = brise;
-      rise[1] = tip_rise(r, T, u_to_t(r, c1));
-      rise[2] = tip_rise(r, T, u_to_t(r, c2));
+      r0 = brise;
+      r1 = tip_rise(r, T, u_to_t(r, c1));
+      r2 = tip_rise(r, T, u_to_t(r, c2));
     } else {
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        rise[k] = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, pa[k]), pb[k])));
+      r0 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, bu0), c1)));
+      r1 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c1), c2)));
+      r2 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c2), bu1)));
     }
-    float nbest = SS_INF, n0 = bu0, n1 = bu1, nrise = brise;
-    int nx = 2 * bx, ny = 2 * by, nh = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float u = pa[k], v = pb[k];
-      const float um = 0.5f * (u + v);
-      const int ccx = 2 * bx + ((r.Kx * um >= mxr) ? 1 : 0);
-      const int ccy = 2 * by + ((r.Ky * um >= myr) ? 1 : 0);
-      const float lb = lower_bound_at(T, rise[k], lv - 1, ccx, ccy, r.hp);
-      // children beyond a ragged edge are absent
-      const bool ok = v > u && ccx < T.lw[lv - 1] && ccy < T.lh[lv - 1];
-      n_lb += ok ? 1u : 0u;
-      if (ok && lb <= nbest) {
-        nbest = lb;
-        nx = ccx;
-        ny = ccy;
-        n0 = u;
-        n1 = v;
-        nrise = rise[k];
-        nh = 1;
-      }
-    }
-    if (!nh) return;
-    bx = nx;
-    by = ny;
-    bu0 = n0;
-    bu1 = n1;
-    brise = nrise;
+    // children beyond a ragged edge are absent
+    const int cw = T.lw[lv - 1], ch = T.lh[lv - 1];
+    const bool ok0 = c1 > bu0 && x0 < cw && y0 < ch;
+    const bool ok1 = c2 > c1 && x1 < cw && y1 < ch;
+    const bool ok2 = bu1 > c2 && x2 < cw && y2 < ch;
+    const float lb0 = ok0 ? r0 - (M0 - r.hp) : SS_INF;
+    const float lb1 = ok1 ? r1 - (M1 - r.hp) : SS_INF;
+    const float lb2 = ok2 ? r2 - (M2 - r.hp) : SS_INF;
+    n_lb += (ok0 ? 1u : 0u) + (ok1 ? 1u : 0u) + (ok2 ? 1u : 0u);
+    // strict argmin from the far end == '<=' from the near end
+    int k = ok0 ? 0 : -1;
+    float bl = lb0;
+    if (ok1 && (k < 0 || lb1 <= bl)) { k = 1; bl = lb1; }
+    if (ok2 && (k < 0 || lb2 <= bl)) { k = 2; bl = lb2; }
+    if (k < 0) return;
+    bx = k == 0 ? x0 : (k == 1 ? x1 : x2);
+    by = k == 0 ? y0 : (k == 1 ? y1 : y2);
+    brise = k == 0 ? r0 : (k == 1 ? r1 : r2);
+    const float nu0 = k == 0 ? bu0 : (k == 1 ? c1 : c2);
+    const float nu1 = k == 0 ? c1 : (k == 1 ? c2 : bu1);
+    bu0 = nu0;
+    bu1 = nu1;
   }
   // final samples on the half-texel grid t_n = (n + 1) delta/2 around the
   // middle of the base texel's stretch of ray
