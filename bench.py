@@ -106,6 +106,83 @@ def cpu_baseline(h_np, params_or, seconds=15.0):
                       f"{threads} host threads ({cpu}), {dt:.1f} s"}
 
 
+def _csv_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir, counters_dir, out_dir):
+    """Turns rocprofv3 CSV output of this benchmark into the committed summaries:
+    per-kernel durations, HBM bytes per launch (FETCH_SIZE/WRITE_SIZE scaled by
+    the same counters on the 512 MiB calibration copy) and VALU counters."""
+    import collections
+    os.makedirs(out_dir, exist_ok=True)
+    lines = []
+    stats = _csv_rows(os.path.join(trace_dir, "bench_kernel_stats.csv"))
+    lines.append("kernel | calls | avg us | total ms")
+    for r in stats[:12]:
+        lines.append(f"{r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f}")
+    with open(os.path.join(out_dir, "bench_tile_kernel_stats.txt"), "w") as f:
+        f.write("# rocprofv3 --kernel-trace --stats summary of the tile benchmark\n")
+        f.write("# command: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
+                "python bench.py --steps 5 --warmup 1 --no-cpu --dem-cache /tmp/dem_tile.npy\n")
+        f.write("\n".join(lines) + "\n")
+
+    def per_kernel(d, counter):
+        acc = collections.defaultdict(list)
+        for r in _csv_rows(os.path.join(d, "bench_counter_collection.csv")):
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return acc
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    copy_bytes = 512 * 1024 * 1024 / 1024.0  # KiB moved each way by the calibration copy
+    cal_f = copy_bytes / max(fetch["__amd_rocclr_copyBuffer"])
+    cal_w = copy_bytes / max(write["__amd_rocclr_copyBuffer"])
+    out = {"kernel_src_sha": src_hash(DP_SOURCES), "fetch_scale": cal_f, "write_scale": cal_w,
+           "kernels": {}}
+    for name in fetch:
+        if not name.startswith("void ss::"):
+            continue
+        fb = sum(fetch[name]) / len(fetch[name]) * 1024 * cal_f
+        wb = sum(write.get(name, [0.0])) / max(1, len(write.get(name, []))) * 1024 * cal_w
+        out["kernels"][name] = {"launches": len(fetch[name]), "fetch_bytes": fb,
+                                "write_bytes": wb}
+    dp = [k for k in out["kernels"] if "shadow_kernel<true, 8, 0, false>" in k]
+    if dp:
+        k = out["kernels"][dp[0]]
+        out["hbm_bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
+    out["command"] = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-include-regex 'ss::|copy' "
+                      "--output-format csv -d <dir> -o bench -- python bench.py --steps 1 --warmup 0 "
+                      "--no-cpu --no-extras --calibrate-copy --dem-cache /tmp/dem_tile.npy")
+    with open(os.path.join(out_dir, "shadow_dp_tile_traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    if counters_dir:
+        acc = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in _csv_rows(os.path.join(counters_dir, "bench_counter_collection.csv")):
+            acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        lines = ["kernel | VALU instr per wave | active lanes per VALU instr | trans per wave | "
+                 "L2 hit rate"]
+        for name, d in acc.items():
+            v = {c: sum(x) / len(x) for c, x in d.items()}
+            waves = v.get("SQ_WAVES", 1.0)
+            hit = v.get("TCC_HIT_sum")
+            miss = v.get("TCC_MISS_sum")
+            hr = f"{hit / (hit + miss):.3f}" if hit is not None and miss is not None else "-"
+            lines.append(f"{name[:70]} | {v.get('SQ_INSTS_VALU', 0) / waves:.0f} | "
+                         f"{v.get('SQ_THREAD_CYCLES_VALU', 0) / max(1.0, v.get('SQ_ACTIVE_INST_VALU', 1)):.1f} | "
+                         f"{v.get('SQ_INSTS_VALU_TRANS_F32', 0) / waves:.0f} | {hr}")
+        with open(os.path.join(out_dir, "shadow_dp_tile_counters.txt"), "w") as f:
+            f.write("# rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU "
+                    "SQ_INSTS_VALU_TRANS_F32 TCC_HIT_sum TCC_MISS_sum --kernel-include-regex "
+                    "shadow_kernel --output-format csv -d <dir> -o bench -- python bench.py --steps 1 "
+                    "--warmup 0 --no-cpu --no-extras --dem-cache /tmp/dem_tile.npy\n")
+            f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,7 +194,12 @@ def main():
                     help="run a 512 MiB device copy first (counter calibration)")
     ap.add_argument("--dem-cache", default="",
                     help="load the DEM from this .npy if present, else generate and save it")
+    ap.add_argument("--summarize", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COUNTERS", "OUT"),
+                    help="write profile summaries from rocprofv3 CSV directories and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize_profiles(*args.summarize)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the path would "
               "shard by replicating the DEM and its mipmap and splitting ray blocks across GPUs, "
