@@ -183,13 +183,164 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, counters_dir, out_dir):
             f.write("\n".join(lines) + "\n")
 
 
+def _pct(xs):
+    import numpy as np
+    return [float(v) for v in np.percentile(np.asarray(xs, dtype=np.float64), [10, 50, 90])]
+
+
+def _timed(fn, reps):
+    """Per-repetition milliseconds of fn() between events on the current stream."""
+    import torch
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        fn()
+        b.record(st)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return ts
+
+
+def _err_stats(x, ref):
+    """mean, 99th percentile and fraction above 0.05 of |x - ref|."""
+    d = (x - ref).abs().flatten()
+    ds, _ = d.sort()
+    p99 = float(ds[min(ds.numel() - 1, int(0.99 * ds.numel()))])
+    return {"mean_abs": float(d.mean()), "p99_abs": p99, "frac_gt_0.05": float((d > 0.05).float().mean())}
+
+
+def leg_accuracy(ss, h, mm, D, suns, c):
+    """Image error of the descent and of one-texel uniform stepping against
+    dense stepping on the half-texel grid (the grid the descent's final samples
+    use), over every sun of the workload."""
+    import torch
+    from synth import R_MOON
+    pd = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"])
+    pu1 = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
+    pu2 = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM,
+                    uniform_step=0.5)
+    dp, u1, u2 = [], [], []
+    for (e, a, r) in suns:
+        dp.append(ss.shadow_cast(h, D, e, a, r, pd, mm=mm))
+        u1.append(ss.shadow_cast(h, D, e, a, r, pu1, mm=mm))
+        u2.append(ss.shadow_cast(h, D, e, a, r, pu2, mm=mm))
+    dp, u1, u2 = torch.stack(dp), torch.stack(u1), torch.stack(u2)
+    return {"reference": "uniform stepping at delta/2 (dense half-texel grid), all suns",
+            "descent": _err_stats(dp, u2), "uniform_1_texel": _err_stats(u1, u2),
+            "mean_s_dense": float(u2.mean())}
+
+
+def leg_cold_maxmip(ss, h, mm, mm_bytes, reps=5):
+    """Mipmap build after streaming 1 GiB through the caches (L2 and MALL cold)."""
+    import torch
+    scratch = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=h.device)
+    ts = []
+    for i in range(reps):
+        scratch.fill_(float(i))
+        ts += _timed(lambda: ss.maxmip(h, out=mm), 1)
+    del scratch
+    ms = float(sum(ts) / len(ts))
+    return {"avg_launch_ms": ms, "achieved_GBs": mm_bytes / (ms / 1e3) / 1e9,
+            "frac": mm_bytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS}
+
+
+def leg_diff(ss, reps=5):
+    """The 2048^2 differentiable workload: forward and forward+adjoint rays/s."""
+    import torch
+    from synth import config, dem_for, sun_list, R_MOON
+    c = config("diff")
+    W, H, D = c["tiles"][0]
+    e, a, r = sun_list("diff")[0]
+    h = dem_for("diff", device="cuda")
+    mm = ss.maxmip(h)
+    p = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"])
+    out = torch.empty_like(h)
+    g = torch.randn(H, W, generator=torch.Generator(device="cpu").manual_seed(11)).to(h.device)
+    gh = torch.zeros_like(h)
+    gs = torch.zeros(2, dtype=torch.float64, device=h.device)
+
+    def fwd():
+        ss.maxmip(h, out=mm)
+        ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out)
+
+    def fwd_bwd():
+        fwd()
+        ss.shadow_cast_backward(h, D, e, a, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+
+    fwd_bwd()
+    tf = _timed(fwd, reps)
+    tb = _timed(fwd_bwd, reps)
+    n = W * H
+    return {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
+            "fwd_ms": min(tf), "fwd_bwd_ms": min(tb)}
+
+
+def leg_batched(ss, reps=3):
+    """8 uneven tiles x 64 suns through one captured graph (mipmaps + persistent kernel)."""
+    from synth import config, dem_for, sun_list, R_MOON
+    c = config("batched")
+    heights = [dem_for("batched", t, device="cuda") for t in range(len(c["tiles"]))]
+    texels = [tx for (_, _, tx) in c["tiles"]]
+    suns = sun_list("batched")
+    plan = ss.BatchedPlan(heights, texels, suns, ss.Params(radius_m=R_MOON, max_len_m=c["max_len"]))
+    plan.launch()
+    ts = _timed(plan.launch, reps)
+    rays = sum(w * r for (w, r, _) in c["tiles"]) * len(suns)
+    rt, fd = plan.config()
+    plan.close()
+    del plan, heights
+    return {"rays": rays, "graph_launch_ms": min(ts), "mrays_s": rays / (min(ts) / 1e3) / 1e6,
+            "ray_tile": rt, "fuse_depth": fd}
+
+
+def leg_polar(ss, reps=3):
+    """16384^2 at 2 m/texel, sun at 0.2 degrees, 60 km rays: forward and forward+adjoint."""
+    import torch
+    from synth import config, dem_for, sun_list, R_MOON
+    c = config("polar")
+    W, H, D = c["tiles"][0]
+    e, a, r = sun_list("polar")[0]
+    h = dem_for("polar", device="cuda")
+    mm = ss.maxmip(h)
+    p = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"])
+    out = torch.empty_like(h)
+
+    def fwd():
+        ss.maxmip(h, out=mm)
+        ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out)
+
+    fwd()
+    tf = _timed(fwd, reps)
+    g = torch.ones_like(h)
+    gh = torch.zeros_like(h)
+    gs = torch.zeros(2, dtype=torch.float64, device=h.device)
+
+    def fwd_bwd():
+        fwd()
+        ss.shadow_cast_backward(h, D, e, a, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+
+    tb = _timed(fwd_bwd, 1)
+    n = W * H
+    res = {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
+           "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "mean_s": float(out.mean())}
+    del h, mm, out, g, gh
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip uniform and backward legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip every leg beside the headline step (uniform, accuracy, backward, "
+                         "cold mipmap, batched, polar, differentiable)")
+    ap.add_argument("--no-big", action="store_true",
+                    help="skip the batched (8 tiles x 64 suns) and polar (16384^2) legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration)")
     ap.add_argument("--dem-cache", default="",
@@ -269,6 +420,7 @@ def main():
     maxmip_ms = [a.elapsed_time(b) for a, b in ev_mm]
     avg_dp_ms = float(np.mean(launch_ms))
     avg_mm_ms = float(np.mean(maxmip_ms))
+    step_ms = [ev_mm[i][0].elapsed_time(ev_dp[i][-1][1]) for i in range(args.steps)]
 
     # algorithmic units per launch (instrumented twin of the same kernel, untimed)
     units = []
@@ -293,8 +445,10 @@ def main():
               "frac": mm_bytes / (avg_mm_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
               "note": "64 MiB source is L2/MALL resident between steps (warm)"}
 
-    extras = {}
+    extras = {"step_ms_p10_p50_p90": _pct(step_ms), "launch_ms_p10_p50_p90": _pct(launch_ms)}
     if not args.no_extras:
+        extras["accuracy_vs_dense"] = leg_accuracy(ss, h, mm, D, suns, c)
+        maxmip["cold"] = leg_cold_maxmip(ss, h, mm, mm_bytes)
         # uniform stepping, one texel per step, same suns, cap and exits
         pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
         for k, (e, a, r) in enumerate(suns[:1]):
@@ -328,6 +482,10 @@ def main():
             torch.cuda.synchronize()
             tfb = time.perf_counter() - t0
         extras["fwd_bwd_mrays_s"] = rays_per_step / tfb / 1e6
+        extras["differentiable_2048"] = leg_diff(ss)
+        if not args.no_big:
+            extras["batched_8x64"] = leg_batched(ss)
+            extras["polar_16384"] = leg_polar(ss)
 
     cpu = None
     if not args.no_cpu:

@@ -10,5 +10,5 @@ torch float64 autograd (``grad_ref.py``).
 """
 from .core import (  # noqa: F401
     Params, build, load, maxmip_levels, maxmip, shadow, shadow_threaded, alternatives,
-    disc_fraction, schedule, ray_consts, probe, path_cells, TRACE_DTYPE,
+    disc_fraction, schedule, ray_consts, probe, path_cells, tap_bound, TRACE_DTYPE,
 )

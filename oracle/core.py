@@ -172,6 +172,29 @@ def maxmip(h: np.ndarray) -> list:
     return out
 
 
+def tap_bound(h: np.ndarray) -> list:
+    """Tap-bound pyramid of h: [level 0, level 1, ...] as float32 arrays.
+
+    A bilinear sample at continuous texel position q (texel i covers [i, i+1))
+    reads the texels floor(q - 1/2) and floor(q - 1/2) + 1 per axis, clamped to
+    the tile (Sec. 3.4 samples the terrain bilinearly).  For q anywhere in
+    texel (x, y), or up to half a texel outside it, those taps lie in the 3 x 3
+    block of texels around (x, y).  Level 0 therefore holds, per texel, the
+    largest height of that block clipped to the tile; levels >= 1 are the
+    maximum mipmap of level 0 (Sec. 3.2).  -0 is stored as +0.
+    """
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    rows, width = h.shape
+    pad = np.full((rows + 2, width + 2), -np.inf, dtype=np.float32)
+    pad[1:-1, 1:-1] = h
+    d0 = np.full((rows, width), -np.inf, dtype=np.float32)
+    for dy in (0, 1, 2):
+        for dx in (0, 1, 2):
+            d0 = np.maximum(d0, pad[dy:dy + rows, dx:dx + width])
+    d0 = d0 + np.float32(0.0)  # -0 -> +0
+    return [d0] + maxmip(d0)
+
+
 def shadow(h: np.ndarray, p: Params, rays=None, trace: bool = False, _c=None):
     """Shadow factor s (float64) for all texels ([rows, width]) or the given linear indices."""
     h = np.ascontiguousarray(h, dtype=np.float32)

@@ -529,10 +529,12 @@ static double shadow_dp(const ray_t* r, or_trace* tr) {
 }
 
 /* Uniform stepping (Sec. 2 and Fig. 1b; the paper's baseline in Sec. 6.3):
- * constant steps along the ray, clearance angle at every step, minimum. */
-static double shadow_uniform(const ray_t* r, or_trace* tr) {
+ * constant steps du along the ray, clearance angle at every step, minimum.
+ * With du = delta/2 the steps are exactly the half-texel grid t_n = (n+1)
+ * delta/2 on which the descent places its final samples, so the minimum is
+ * the global minimum over that grid (the exact mode's definition). */
+static double shadow_uniform(const ray_t* r, double du, or_trace* tr) {
   const setup_t* s = r->s;
-  double du = s->p->uniform_step * s->delta;
   double alpha = INFINITY;
   or_trace t0;
   memset(&t0, 0, sizeof(t0));
@@ -575,7 +577,13 @@ int32_t or_shadow(const or_ctx* c, const or_params* p, const int64_t* rays, int6
     ray_t r;
     or_ray_init(&r, &s, (int)(lin % c->W), (int)(lin / c->W));
     or_trace tr;
-    double alpha = p->mode == 1 ? shadow_uniform(&r, &tr) : shadow_dp(&r, &tr);
+    double alpha;
+    if (p->mode == 1)
+      alpha = shadow_uniform(&r, p->uniform_step * s.delta, &tr);
+    else if (p->mode == 2)
+      alpha = shadow_uniform(&r, 0.5 * s.delta, &tr);
+    else
+      alpha = shadow_dp(&r, &tr);
     double sv = 1.0;
     if (isfinite(alpha)) {
       double d = alpha / p->ang_radius_rad;

@@ -33,7 +33,8 @@ typedef struct {
   int32_t n_prime0;       /* mip levels traced by the first segment */
   int32_t schedule;       /* 0: N'_j = N'_0 + j (geometric); 1: N'_j = N'_0 (equal) */
   int32_t n_segments;     /* > 0 overrides the segment count derived from the cap */
-  int32_t mode;           /* 0: dynamic-programming descent; 1: uniform stepping */
+  int32_t mode;           /* 0: dynamic-programming descent; 1: uniform stepping;
+                             2: exact minimum over the half-texel grid (dense stepping) */
   double uniform_step;    /* uniform step, texels of horizontal travel */
   double uniform_tmax_m;  /* > 0 overrides the uniform cap on ray length t */
 } or_params;

@@ -38,7 +38,7 @@ def fbm_like(shape, seed, amp):
 
 @pytest.mark.parametrize("radius,elev", [(math.inf, RL * 1.001), (math.inf, math.radians(3)),
                                          (R, math.radians(0.3)), (R, math.radians(2.0))])
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_flat_ground_is_lit(orc, radius, elev, mode):
     h = np.zeros((64, 64), np.float32)
     for a in (0.0, 0.7, 2.5, 4.0):
@@ -47,7 +47,7 @@ def test_flat_ground_is_lit(orc, radius, elev, mode):
         assert np.all(s == 1.0)
 
 
-@pytest.mark.parametrize("mode,step", [(0, 1.0), (1, 1.0), (1, 0.5)])
+@pytest.mark.parametrize("mode,step", [(0, 1.0), (1, 1.0), (1, 0.5), (2, 1.0)])
 def test_half_set_sun(orc, mode, step):
     """Plane, h = 0, e = 0.2 deg < r_L: every sample's clearance is exactly e."""
     e = math.radians(0.2)
@@ -70,7 +70,7 @@ def ridge_case(e_deg):
 
 
 @pytest.mark.parametrize("e_deg", [1.5, 3.0])
-@pytest.mark.parametrize("mode,step", [(0, 1.0), (1, 0.5)])
+@pytest.mark.parametrize("mode,step", [(0, 1.0), (1, 0.5), (2, 1.0)])
 def test_straight_ridge_penumbra(orc, e_deg, mode, step):
     """Plane, sun along +column, one-texel ridge: s(x) = S((e - atan(h_r/x))/r_L)."""
     h, W, rows, D, ir, hr, e = ridge_case(e_deg)
