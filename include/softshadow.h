@@ -40,6 +40,9 @@ extern "C" {
 
 #define SS_MODE_DP 0             /* dynamic-programming descent (Sec. 3.2, Alg. 1) */
 #define SS_MODE_UNIFORM 1        /* uniform stepping baseline (Sec. 2, Fig. 1b; Sec. 6.3) */
+#define SS_MODE_EXACT 2          /* exact minimum over the half-texel sample grid of Alg. 1's
+                                    final samples, by branch and bound over the tap-bound
+                                    pyramid (Sec. 2: global minimisation) */
 
 #define SS_SCHED_GEOMETRIC 0     /* segment j traces N'_0 + j levels (capped at the mipmap) */
 #define SS_SCHED_EQUAL 1         /* every segment traces N'_0 levels (the paper's {5,5,5}) */
@@ -67,12 +70,15 @@ typedef struct {
 } ss_params;
 
 /* One heightfield tile.  `maxmip` holds levels >= 1 of its maximum mipmap in
- * the packed layout below (built by ss_maxmip_build). */
+ * the packed layout below (built by ss_maxmip_build); `bound` holds its
+ * tap-bound pyramid (built by ss_bound_build), read by SS_MODE_EXACT only and
+ * may be NULL otherwise. */
 typedef struct {
   const float* height;     /* device, [rows][width] */
   const float* maxmip;     /* device, ss_maxmip_floats(width, rows) floats */
   int32_t width, rows;     /* >= 1 */
   double texel_m;          /* > 0 */
+  const float* bound;      /* device, ss_bound_floats(width, rows) floats, or NULL */
 } ss_tile;
 
 /* ---- maximum mipmap (Sec. 3.2, "Maximum mipmaps") ------------------------ */
@@ -94,24 +100,45 @@ int64_t ss_maxmip_floats(int32_t width, int32_t rows);
 int32_t ss_maxmip_build(const float* d_height, int32_t width, int32_t rows, float* d_maxmip,
                         int32_t fuse_depth, void* stream);
 
+/* ---- tap-bound pyramid (for SS_MODE_EXACT) ------------------------------- */
+
+/* A bilinear sample (Sec. 3.4) located anywhere in texel (x, y), or up to half
+ * a texel outside it, reads only texels of the 3 x 3 block around (x, y).
+ * Level 0 of the tap-bound pyramid holds, per texel, the largest height of that
+ * block clipped to the tile; level m >= 1 is the maximum mipmap of level 0
+ * (Sec. 3.2), so a level-m entry bounds every tap of every sample that falls in
+ * its 2^m x 2^m texels.  Layout: level 0 ([rows][width]) at float offset 0,
+ * level m >= 1 at ss_bound_level_offset(width, rows, m) = B +
+ * ss_maxmip_level_offset(width, rows, m) with B = width*rows rounded up to a
+ * multiple of 64; ss_bound_floats is the total (-1 for invalid sizes).  -0 is
+ * stored as +0.  Bit-exact; sun-independent, so it is built once per tile. */
+int64_t ss_bound_floats(int32_t width, int32_t rows);
+int64_t ss_bound_level_offset(int32_t width, int32_t rows, int32_t level);
+int32_t ss_bound_build(const float* d_height, int32_t width, int32_t rows, float* d_bound,
+                       void* stream);
+
 /* ---- shadow factor (Sec. 3.1-3.4, Alg. 1) -------------------------------- */
 
 /* For every texel centre p: cast the shadow ray p + t L toward the sun centre,
  * find the clearance by the segment schedule (Sec. 3.3) and the descent through
- * the maximum mipmap (Sec. 3.2) -- or by uniform steps in SS_MODE_UNIFORM --,
+ * the maximum mipmap (Sec. 3.2) -- or by uniform steps in SS_MODE_UNIFORM, or
+ * as the exact minimum over the half-texel grid t_n = (n+1) delta/2 in
+ * SS_MODE_EXACT (bit-identical to SS_MODE_UNIFORM with uniform_step 0.5) --,
  * and write the visible fraction of the sun disc (Sec. 3.4, Eq. 6 circular
  * segment) to d_shadow[j*width + i] in [0, 1] (1 = fully lit).  Overwrites
- * d_shadow.  tile->maxmip must hold the built mipmap of tile->height. */
+ * d_shadow.  tile->maxmip must hold the built mipmap of tile->height, and in
+ * SS_MODE_EXACT tile->bound its tap-bound pyramid (NULL: SS_ERR_INVALID_ARG). */
 int32_t ss_shadow_cast(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                        float* d_shadow, void* stream);
 
 /* Instrumented variant: same output; adds the number of max-mip lower-bound
- * evaluations to d_eval_count[0] and of bilinear clearance samples (the
- * descent's final samples, or uniform steps) to d_eval_count[1]. */
+ * evaluations (SS_MODE_EXACT: tap-bound tests) to d_eval_count[0] and of
+ * bilinear clearance samples (the descent's final samples, uniform steps, or
+ * the exact mode's evaluated grid samples) to d_eval_count[1]. */
 int32_t ss_shadow_cast_counted(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                                float* d_shadow, unsigned long long* d_eval_count, void* stream);
 
-/* Adjoint of ss_shadow_cast (SS_MODE_DP only).  Recomputes every ray's
+/* Adjoint of ss_shadow_cast (every mode).  Recomputes every ray's
  * decisions, then ACCUMULATES (+=) dL/dh into d_grad_height [rows][width] and
  * dL/d(elev, azim) into d_grad_sun[2] (FP64), given dL/ds in d_grad_shadow.
  * The max-mipmap enters only through discrete choices and has zero gradient.
@@ -129,7 +156,8 @@ int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns);
  * (host array of device pointers, each [rows_t][width_t]) for tile t and sun
  * k in one persistent launch that takes (tile, sun, ray block) items from a
  * queue in d_workspace.  Outputs are bit-identical to ss_shadow_cast with the
- * same parameters.  d_workspace is used for the duration of the call. */
+ * same parameters.  d_workspace is used for the duration of the call.
+ * SS_MODE_DP and SS_MODE_UNIFORM (SS_MODE_EXACT: SS_ERR_UNSUPPORTED). */
 int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
                                int32_t n_suns, const ss_params* params, float* const* d_shadow,
                                void* d_workspace, int64_t workspace_bytes, void* stream);

@@ -535,7 +535,7 @@ static double shadow_dp(const ray_t* r, or_trace* tr) {
  * the global minimum over that grid (the exact mode's definition). */
 static double shadow_uniform(const ray_t* r, double du, or_trace* tr) {
   const setup_t* s = r->s;
-  double alpha = INFINITY;
+  double alpha = INFINITY, second = INFINITY;
   or_trace t0;
   memset(&t0, 0, sizeof(t0));
   t0.seg = -2;
@@ -552,15 +552,28 @@ static double shadow_uniform(const ray_t* r, double du, or_trace* tr) {
     double a = or_alpha_of(r, t, dh);
     t0.evals++;
     if (a < alpha) {
+      second = alpha;
       alpha = a;
       t0.seg = -1;
       t0.n = (int32_t)k;
       t0.t = t;
       t0.dh = dh;
+    } else if (a < second) {
+      second = a;
     }
   }
   t0.alpha = alpha;
+  /* how clearly the deciding step wins (rad), and its distance from a line
+   * through texel centres (where the bilinear slope jumps) per texel travelled */
+  t0.margin_seg = second - alpha;
   t0.margin_tap = INFINITY;
+  if (t0.n >= 0) {
+    double qx, qy, Hd;
+    or_ray_point(r, t0.t, &qx, &qy, &Hd);
+    double fx = qx - 0.5 - floor(qx - 0.5), fy = qy - 0.5 - floor(qy - 0.5);
+    double m = fmin(fmin(fx, 1.0 - fx), fmin(fy, 1.0 - fy));
+    t0.margin_tap = m / (1.0 + t0.t / s->delta);
+  }
   if (tr) *tr = t0;
   return alpha;
 }

@@ -50,7 +50,8 @@ typedef struct {
   double margin_lb;      /* smallest best/runner-up gap of any lower-bound argmin (m) */
   double margin_dh;      /* smallest best/runner-up gap of any final-sample argmin (m) */
   double margin_round;   /* smallest distance of a rounding argument from its boundary */
-  double margin_seg;     /* gap between the two smallest segment clearances (rad) */
+  double margin_seg;     /* gap between the two smallest segment clearances (rad);
+                            stepping modes: between the two smallest step clearances */
   double margin_geo;     /* smallest spacing of crossing events / (1 + texels travelled) */
   double margin_tap;     /* distance of the deciding sample from a tap line / (1 + texels travelled) */
 } or_trace;

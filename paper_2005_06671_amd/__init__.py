@@ -6,6 +6,8 @@ from .api import (  # noqa: F401
     Params, maxmip, maxmip_levels, maxmip_floats, maxmip_level_offset, maxmip_unpack,
     shadow_cast, shadow_cast_counted, shadow_cast_backward, shadow, ShadowCast,
     shadow_cast_batched, batched_workspace_bytes, BatchedPlan, SUN_RADIUS_RAD,
+    bound_build, bound_floats, bound_level_offset, bound_unpack,
 )
 from ._lib import lib, SoftShadowError, RAY_TILES, SS_MODE_DP, SS_MODE_UNIFORM  # noqa: F401
+from ._lib import SS_MODE_EXACT  # noqa: F401
 from ._lib import SS_SCHED_EQUAL, SS_SCHED_GEOMETRIC  # noqa: F401

@@ -15,6 +15,7 @@ SS_ERR_WORKSPACE = -3
 SS_ERR_UNSUPPORTED = -4
 SS_MODE_DP = 0
 SS_MODE_UNIFORM = 1
+SS_MODE_EXACT = 2
 SS_SCHED_GEOMETRIC = 0
 SS_SCHED_EQUAL = 1
 RAY_TILES = {"8x8": 1, "16x4": 2, "4x16": 3, "32x2": 4}
@@ -32,7 +33,7 @@ class SSParams(C.Structure):
 
 class SSTile(C.Structure):
     _fields_ = [("height", C.c_void_p), ("maxmip", C.c_void_p), ("width", C.c_int32),
-                ("rows", C.c_int32), ("texel_m", C.c_double)]
+                ("rows", C.c_int32), ("texel_m", C.c_double), ("bound", C.c_void_p)]
 
 
 # Every exported symbol with (restype, argtypes); the CPU tests check that this
@@ -43,6 +44,9 @@ SIGNATURES = {
     "ss_maxmip_floats": (C.c_int64, [C.c_int32, C.c_int32]),
     "ss_maxmip_build": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
                                     C.c_void_p]),
+    "ss_bound_floats": (C.c_int64, [C.c_int32, C.c_int32]),
+    "ss_bound_level_offset": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
+    "ss_bound_build": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "ss_shadow_cast": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
                                    C.c_void_p, C.c_void_p]),
     "ss_shadow_cast_counted": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun),

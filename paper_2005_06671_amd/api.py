@@ -84,9 +84,49 @@ def maxmip_unpack(mm: torch.Tensor, width: int, rows: int) -> list:
     return out
 
 
-def _tile(h: torch.Tensor, mm: torch.Tensor, texel_m: float) -> L.SSTile:
+def bound_floats(width: int, rows: int) -> int:
+    return L.lib().ss_bound_floats(width, rows)
+
+
+def bound_level_offset(width: int, rows: int, level: int) -> int:
+    return L.lib().ss_bound_level_offset(width, rows, level)
+
+
+def bound_build(h: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Tap-bound pyramid of h (ss_bound_build), packed (ss_bound_level_offset)."""
+    _dev_f32_2d(h)
     rows, width = h.shape
-    return L.SSTile(h.data_ptr(), mm.data_ptr(), width, rows, float(texel_m))
+    n = max(1, bound_floats(width, rows))
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=h.device)
+    elif out.numel() < n or out.dtype != torch.float32 or not out.is_cuda:
+        raise ValueError("out is too small or not float32 CUDA")
+    L.check("ss_bound_build", L.lib().ss_bound_build(h.data_ptr(), width, rows, out.data_ptr(),
+                                                     _stream(h.device)))
+    return out
+
+
+def bound_unpack(b: torch.Tensor, width: int, rows: int) -> list:
+    """Views of levels 0..L-1 of a packed tap-bound pyramid as [rows_m, width_m] tensors."""
+    out = [b[:width * rows].view(rows, width)]
+    w, r = width, rows
+    for m in range(1, maxmip_levels(width, rows)):
+        w, r = (w + 1) // 2, (r + 1) // 2
+        off = bound_level_offset(width, rows, m)
+        out.append(b[off:off + w * r].view(r, w))
+    return out
+
+
+def _tile(h: torch.Tensor, mm: torch.Tensor, texel_m: float, bound=None) -> L.SSTile:
+    rows, width = h.shape
+    return L.SSTile(h.data_ptr(), mm.data_ptr(), width, rows, float(texel_m),
+                    bound.data_ptr() if bound is not None else None)
+
+
+def _bound_for(h, params, bound):
+    if bound is None and params.mode == L.SS_MODE_EXACT:
+        bound = bound_build(h)
+    return bound
 
 
 def _sun(elev: float, azim: float, ang_radius: float) -> L.SSSun:
@@ -95,15 +135,18 @@ def _sun(elev: float, azim: float, ang_radius: float) -> L.SSSun:
 
 def shadow_cast(h: torch.Tensor, texel_m: float, elev: float, azim: float,
                 ang_radius: float = SUN_RADIUS_RAD, params: Params | None = None,
-                mm: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Shadow factor s in [0, 1] for every texel of h (builds the mipmap if mm is None)."""
+                mm: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                bound: torch.Tensor | None = None) -> torch.Tensor:
+    """Shadow factor s in [0, 1] for every texel of h (builds the mipmap if mm is
+    None, and in the exact mode the tap-bound pyramid if bound is None)."""
     _dev_f32_2d(h)
     params = params or Params()
     if mm is None:
         mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
     if out is None:
         out = torch.empty_like(h)
-    t = _tile(h, mm, texel_m)
+    t = _tile(h, mm, texel_m, bound)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast", L.lib().ss_shadow_cast(C.byref(t), C.byref(s), C.byref(p),
@@ -112,16 +155,17 @@ def shadow_cast(h: torch.Tensor, texel_m: float, elev: float, azim: float,
 
 
 def shadow_cast_counted(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=None, mm=None,
-                        out=None):
+                        out=None, bound=None):
     """(s, [lower-bound evaluations, bilinear samples]) of one forward launch."""
     _dev_f32_2d(h)
     params = params or Params()
     if mm is None:
         mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
     if out is None:
         out = torch.empty_like(h)
     cnt = torch.zeros(2, dtype=torch.int64, device=h.device)
-    t = _tile(h, mm, texel_m)
+    t = _tile(h, mm, texel_m, bound)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast_counted",
@@ -131,18 +175,19 @@ def shadow_cast_counted(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, param
 
 
 def shadow_cast_backward(h, texel_m, elev, azim, grad_s, ang_radius=SUN_RADIUS_RAD, params=None,
-                         mm=None, grad_h=None, grad_sun=None):
+                         mm=None, grad_h=None, grad_sun=None, bound=None):
     """Accumulates dL/dh (float32) and dL/d(elev, azim) (float64[2]) for upstream dL/ds."""
     _dev_f32_2d(h)
     _dev_f32_2d(grad_s, "grad_s")
     params = params or Params()
     if mm is None:
         mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
     if grad_h is None:
         grad_h = torch.zeros_like(h)
     if grad_sun is None:
         grad_sun = torch.zeros(2, dtype=torch.float64, device=h.device)
-    t = _tile(h, mm, texel_m)
+    t = _tile(h, mm, texel_m, bound)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast_backward",
@@ -165,17 +210,19 @@ class ShadowCast(torch.autograd.Function):
         a = float(azim)
         hd = h.detach().contiguous()
         mm = maxmip(hd)
-        s = shadow_cast(hd, texel_m, e, a, ang_radius, params, mm=mm)
-        ctx.save_for_backward(hd, mm)
+        bound = _bound_for(hd, params, None)
+        s = shadow_cast(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound)
+        ctx.save_for_backward(hd, mm, bound)
         ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim)
         return s
 
     @staticmethod
     def backward(ctx, grad_s):
-        hd, mm = ctx.saved_tensors
+        hd, mm, bound = ctx.saved_tensors
         texel_m, e, a, ang_radius, params, elev, azim = ctx.cfg
         g = grad_s.contiguous()
-        gh, gsun = shadow_cast_backward(hd, texel_m, e, a, g, ang_radius, params, mm=mm)
+        gh, gsun = shadow_cast_backward(hd, texel_m, e, a, g, ang_radius, params, mm=mm,
+                                        bound=bound)
         ge = gsun[0].to(elev.device) if isinstance(elev, torch.Tensor) else None
         ga = gsun[1].to(azim.device) if isinstance(azim, torch.Tensor) else None
         return gh, ge, ga, None, None, None

@@ -107,6 +107,33 @@ extern "C" int32_t ss_maxmip_build(const float* d_height, int32_t width, int32_t
 }
 
 // ------------------------------------------------------------------------
+// Tap-bound pyramid: level 0 then the maximum mipmap of level 0.
+// ------------------------------------------------------------------------
+
+static int64_t bound_base(int32_t W, int32_t H) { return ((int64_t)W * H + 63) / 64 * 64; }
+
+extern "C" int64_t ss_bound_floats(int32_t width, int32_t rows) {
+  if (!size_ok(width, rows)) return -1;
+  return bound_base(width, rows) + ss_maxmip_floats(width, rows);
+}
+
+extern "C" int64_t ss_bound_level_offset(int32_t width, int32_t rows, int32_t level) {
+  if (!size_ok(width, rows)) return -1;
+  if (level == 0) return 0;
+  const int64_t o = ss_maxmip_level_offset(width, rows, level);
+  return o < 0 ? -1 : bound_base(width, rows) + o;
+}
+
+extern "C" int32_t ss_bound_build(const float* d_height, int32_t width, int32_t rows,
+                                  float* d_bound, void* stream) {
+  if (width == 0 || rows == 0) return (width >= 0 && rows >= 0) ? SS_OK : SS_ERR_INVALID_ARG;
+  if (!size_ok(width, rows) || !d_height || !d_bound) return SS_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  SS_HIP(launch_block3_max(d_height, width, rows, d_bound, s));
+  return maxmip_build(d_bound, width, rows, d_bound + bound_base(width, rows), 6, s);
+}
+
+// ------------------------------------------------------------------------
 // Per-(tile, sun) set-up in FP64 (Sec. 3.3 schedule; Appendix step length).
 // ------------------------------------------------------------------------
 
@@ -123,7 +150,8 @@ static int32_t resolve_params(const ss_params* p, Resolved* r) {
   if (p->n_prime0 < 0 || p->n_prime0 > 64) return SS_ERR_INVALID_ARG;
   if (p->schedule != SS_SCHED_GEOMETRIC && p->schedule != SS_SCHED_EQUAL) return SS_ERR_INVALID_ARG;
   if (p->n_segments < 0) return SS_ERR_INVALID_ARG;
-  if (p->mode != SS_MODE_DP && p->mode != SS_MODE_UNIFORM) return SS_ERR_INVALID_ARG;
+  if (p->mode != SS_MODE_DP && p->mode != SS_MODE_UNIFORM && p->mode != SS_MODE_EXACT)
+    return SS_ERR_INVALID_ARG;
   // 0 = default; otherwise at least 1/64 texel so the step count stays bounded
   if (!(p->uniform_step == 0.0 || p->uniform_step >= 1.0 / 64.0) || isinf(p->uniform_step))
     return SS_ERR_INVALID_ARG;
@@ -140,13 +168,14 @@ static int32_t resolve_params(const ss_params* p, Resolved* r) {
   return SS_OK;
 }
 
-static int32_t check_tile(const ss_tile* t) {
+static int32_t check_tile(const ss_tile* t, int mode) {
   if (!t) return SS_ERR_INVALID_ARG;
   if (t->width < 0 || t->rows < 0) return SS_ERR_INVALID_ARG;
   if (t->width == 0 || t->rows == 0) return SS_OK;
   if (!size_ok(t->width, t->rows) || !t->height) return SS_ERR_INVALID_ARG;
   if (!(t->texel_m > 0.0) || isinf(t->texel_m)) return SS_ERR_INVALID_ARG;
   if (ss_maxmip_floats(t->width, t->rows) > 0 && !t->maxmip) return SS_ERR_INVALID_ARG;
+  if (mode == SS_MODE_EXACT && !t->bound) return SS_ERR_INVALID_ARG;
   return SS_OK;
 }
 
@@ -166,6 +195,8 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
   if (L > SS_MAXLEV) return SS_ERR_UNSUPPORTED;
   K->h = t->height;
   K->mm = t->maxmip;
+  K->bnd = t->bound;
+  K->bmm = t->bound ? t->bound + bound_base(W, H) : nullptr;
   K->W = W;
   K->H = H;
   K->L = L;
@@ -232,11 +263,11 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
 
 static int32_t cast_common(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                            float* d_shadow, unsigned long long* counter, void* stream) {
-  int32_t rc = check_tile(tile);
-  if (rc) return rc;
-  if ((rc = check_sun(sun))) return rc;
   Resolved rp;
-  if ((rc = resolve_params(params, &rp))) return rc;
+  int32_t rc = resolve_params(params, &rp);
+  if (rc) return rc;
+  if ((rc = check_tile(tile, rp.mode))) return rc;
+  if ((rc = check_sun(sun))) return rc;
   if (tile->width == 0 || tile->rows == 0) return SS_OK;
   if (!d_shadow) return SS_ERR_INVALID_ARG;
   TileK K;
@@ -261,18 +292,17 @@ extern "C" int32_t ss_shadow_cast_counted(const ss_tile* tile, const ss_sun* sun
 extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun,
                                            const ss_params* params, const float* d_grad_shadow,
                                            float* d_grad_height, double* d_grad_sun, void* stream) {
-  int32_t rc = check_tile(tile);
-  if (rc) return rc;
-  if ((rc = check_sun(sun))) return rc;
   Resolved rp;
-  if ((rc = resolve_params(params, &rp))) return rc;
-  if (rp.mode != SS_MODE_DP) return SS_ERR_UNSUPPORTED;
+  int32_t rc = resolve_params(params, &rp);
+  if (rc) return rc;
+  if ((rc = check_tile(tile, rp.mode))) return rc;
+  if ((rc = check_sun(sun))) return rc;
   if (tile->width == 0 || tile->rows == 0) return SS_OK;
   if (!d_grad_shadow || !d_grad_height || !d_grad_sun) return SS_ERR_INVALID_ARG;
   TileK K;
   if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
-  SS_HIP(launch_adjoint(K, rp.sphere, sun->elev_rad, sun->azim_rad, d_grad_shadow, d_grad_height,
-                        d_grad_sun, (hipStream_t)stream));
+  SS_HIP(launch_adjoint(K, rp.sphere, rp.mode, sun->elev_rad, sun->azim_rad, d_grad_shadow,
+                        d_grad_height, d_grad_sun, (hipStream_t)stream));
   return SS_OK;
 }
 
@@ -356,9 +386,12 @@ static int32_t check_batch(const ss_tile* tiles, int32_t n_tiles, const ss_sun* 
   if (n_tiles < 0 || n_suns < 0) return SS_ERR_INVALID_ARG;
   if (n_tiles == 0 || n_suns == 0) return SS_OK;
   if (!tiles || !suns || !params || !d_shadow) return SS_ERR_INVALID_ARG;
-  int32_t rc;
+  Resolved rp;
+  int32_t rc = resolve_params(params, &rp);
+  if (rc) return rc;
+  if (rp.mode == SS_MODE_EXACT) return SS_ERR_UNSUPPORTED;
   for (int t = 0; t < n_tiles; ++t) {
-    if ((rc = check_tile(&tiles[t]))) return rc;
+    if ((rc = check_tile(&tiles[t], rp.mode))) return rc;
     if (tiles[t].width == 0 || tiles[t].rows == 0) return SS_ERR_INVALID_ARG;
   }
   for (int k = 0; k < n_suns; ++k)
@@ -369,8 +402,7 @@ static int32_t check_batch(const ss_tile* tiles, int32_t n_tiles, const ss_sun* 
   if (need < 0) return SS_ERR_INVALID_ARG;
   if (!d_workspace || ws_bytes < need) return SS_ERR_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return SS_ERR_WORKSPACE;
-  Resolved rp;
-  return resolve_params(params, &rp);
+  return SS_OK;
 }
 
 // Pinned staging for the tables of eager batched calls.

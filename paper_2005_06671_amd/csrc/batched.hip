@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void batched_kernel(const TileK* __restrict__ 
         if (MODE == SS_MODE_DP)
           alpha = shadow_dp(T, r, top, n_lb, n_smp).alpha;
         else
-          alpha = shadow_uniform(T, r, top, n_smp);
+          alpha = shadow_uniform(T, r, top, n_smp).alpha;
         out[j * T.W + i] = disc_fraction(alpha, T);
       }
     }

@@ -13,6 +13,8 @@
 struct TileK {
   const float* h;            // level 0: the heightfield, [H][W]
   const float* mm;           // levels >= 1, packed at loff[m]
+  const float* bnd;          // tap-bound pyramid level 0, [H][W] (exact mode only)
+  const float* bmm;          // its levels >= 1, packed at loff[m] like mm
   int W, H, L;               // size and number of mip levels (incl. level 0)
   int lw[SS_MAXLEV], lh[SS_MAXLEV];
   int loff[SS_MAXLEV];       // float offset of level m >= 1 inside mm

@@ -10,13 +10,16 @@ namespace ss {
 hipError_t launch_maxmip(const float* src, int sw, int sh, float* dst_base, const int* dst_off,
                          const int* dst_w, const int* dst_h, int F, hipStream_t stream);
 
+// Tap-bound pyramid level 0: maximum over each texel's 3 x 3 block (clipped).
+hipError_t launch_block3_max(const float* src, int W, int H, float* dst, hipStream_t stream);
+
 void grid_for(const TileK& T, int ray_tile, int* nbx, int* nblocks);
 
 hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, bool count,
                           float* out, unsigned long long* counter, hipStream_t stream);
 
-hipError_t launch_adjoint(const TileK& T, bool sphere, double elev, double azim, const float* gs,
-                          float* gh, double* gsun, hipStream_t stream);
+hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
+                          const float* gs, float* gh, double* gsun, hipStream_t stream);
 
 // Persistent batched launch over (tile, sun, ray block) items.
 struct BatchDesc {

@@ -115,6 +115,39 @@ __global__ __launch_bounds__(256) void maxmip_kernel(const float* __restrict__ s
   }
 }
 
+// Tap-bound level 0: the maximum over the 3 x 3 block around each texel,
+// clipped to the tile (repeating the edge row or column gives the same
+// maximum), -0 stored as +0.  One thread per column strip of 8 rows: each row's
+// 3-wide maximum is loaded once and the 3-row window slides down in registers.
+__global__ __launch_bounds__(256) void block3_max_kernel(const float* __restrict__ src, int W, int H,
+                                                         float* __restrict__ dst) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y0 = blockIdx.y * 8;
+  if (x >= W) return;
+  const int xl = max(x - 1, 0), xr = min(x + 1, W - 1);
+  auto row_max = [&](int y) {
+    const float* p = src + (size_t)y * W;
+    return fmaxf(fmaxf(p[xl], p[x]), p[xr]);
+  };
+  float a = row_max(max(y0 - 1, 0));
+  float b = row_max(y0);
+  for (int k = 0; k < 8; ++k) {
+    const int y = y0 + k;
+    if (y >= H) break;
+    const float c = row_max(min(y + 1, H - 1));
+    dst[(size_t)y * W + x] = canon(fmaxf(fmaxf(a, b), c));
+    a = b;
+    b = c;
+  }
+}
+
+hipError_t launch_block3_max(const float* src, int W, int H, float* dst, hipStream_t stream) {
+  if (W <= 0 || H <= 0) return hipSuccess;
+  dim3 grid((W + 255) / 256, (H + 7) / 8), block(256);
+  hipLaunchKernelGGL(block3_max_kernel, grid, block, 0, stream, src, W, H, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_maxmip(const float* src, int sw, int sh, float* dst_base, const int* dst_off,
                          const int* dst_w, const int* dst_h, int F, hipStream_t stream) {
   MipDst d;

@@ -412,7 +412,8 @@ __device__ __forceinline__ float run_top(const TileK& T, const Ray<SPHERE>& r, i
 
 struct RayResult {
   float alpha;
-  float t, u;
+  float key;      // tangent key of alpha (orders like alpha)
+  float t, u;     // deciding sample
   int valid;
 };
 
@@ -450,18 +451,30 @@ __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>
     }
     if (T.prune && best <= -T.tan_rL) break;  // umbra: nothing can change s = 0
   }
+  res.key = best;
   res.alpha = angle_of(best);
   return res;
 }
 
+// Ray length of step k: t_k = delta/2 + k step, rounded once, so that the
+// exact mode (step delta/2) and uniform stepping at half a texel place their
+// samples at bit-identical t.
+__device__ __forceinline__ float step_t(const TileK& T, int k, float step) {
+  return fmaf((float)k, step, T.half_delta);
+}
+
 // Uniform stepping (Sec. 2, Fig. 1b): every step, smallest clearance, kept as
-// a tangent key; atan is taken once.
+// a tangent key; atan is taken once.  The first smallest step decides.
 template <bool SPHERE>
-__device__ __forceinline__ float shadow_uniform(const TileK& T, const Ray<SPHERE>& r, float top,
-                                                unsigned& n_smp) {
+__device__ __forceinline__ RayResult shadow_uniform(const TileK& T, const Ray<SPHERE>& r, float top,
+                                                    unsigned& n_smp) {
+  RayResult res;
+  res.t = 0.0f;
+  res.u = 0.0f;
+  res.valid = 0;
   float best = SS_INF;
-  float t = T.half_delta;
-  for (int k = 0; k < (1 << 22); ++k, t = T.half_delta + (float)k * T.ustep) {
+  for (int k = 0; k < (1 << 22); ++k) {
+    const float t = step_t(T, k, T.ustep);
     if (t > T.ucap) break;
     const float u = t_to_u(r, t);
     if (!(u < r.uexit)) break;
@@ -473,7 +486,117 @@ __device__ __forceinline__ float shadow_uniform(const TileK& T, const Ray<SPHERE
     n_smp++;
     float num, den;
     clearance_terms(r, t, s.dh, num, den);
-    best = fminf(best, tangent_key(num, den));
+    const float key = tangent_key(num, den);
+    if (key < best) {
+      best = key;
+      res.t = t;
+      res.u = u;
+      res.valid = 1;
+    }
   }
-  return angle_of(best);
+  res.key = best;
+  res.alpha = angle_of(best);
+  return res;
+}
+
+// Entry m >= 0 of the tap-bound pyramid: the largest height any bilinear tap
+// of a sample inside level-m texel (cx, cy) can read (also for samples up to
+// half a texel outside it).
+__device__ __forceinline__ float bound_at(const TileK& T, int m, int cx, int cy) {
+  const float* base = m == 0 ? T.bnd : T.bmm + T.loff[m];
+  const int w = (T.W + (1 << m) - 1) >> m;
+  return base[cy * w + cx];
+}
+
+// Exact mode: the smallest clearance over every sample of the grid
+// t_n = (n + 1) delta/2 up to the cap or the tile edge -- the grid of the
+// descent's final samples (Alg. 1), i.e. uniform stepping at half a texel --
+// found by branch and bound over the tap-bound pyramid (the global
+// minimisation of Sec. 2 made exact).  A per-lane walk front to back over
+// the sample index n and a pyramid level m:
+//   * the level-m texel holding sample n bounds the terrain under every
+//     sample whose position lies in it; if the point at that height below the
+//     tip at t_n already clears the angle that could still matter, every
+//     sample up to the texel's exit is skipped and the walk climbs a level;
+//   * otherwise it descends a level, and at level 0 evaluates sample n.
+// Every iteration either advances n or lowers m, so the walk ends.  The skips
+// use the same margin as the other result-invariant exits, so the output is
+// bit-identical to uniform stepping at half a texel (prune = 0 evaluates
+// every sample).
+//
+// Branch and bound prunes best with a good incumbent: the descent (Sec. 3.2)
+// runs first and its deciding sample, a sample of the same grid computed by
+// the same arithmetic, seeds the minimum when it lies within the cap.  A ray
+// the descent already finds in umbra is then done.
+template <bool SPHERE>
+__device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHERE>& r, float top,
+                                                  unsigned& n_tst, unsigned& n_smp) {
+  RayResult res;
+  res.t = 0.0f;
+  res.u = 0.0f;
+  res.valid = 0;
+  float best = SS_INF;
+  if (T.prune) {
+    unsigned n_lb = 0, n_dp = 0;
+    const RayResult d = shadow_dp(T, r, top, n_lb, n_dp);
+    n_tst += n_lb;
+    n_smp += n_dp;
+    if (d.valid && d.t <= T.ucap) {
+      res = d;
+      best = d.key;
+    }
+  }
+  float need = need_tangent(T, best);
+  const int mtop = T.L - 1;
+  const int ex = r.Kx >= 0.0f ? 1 : 0, ey = r.Ky >= 0.0f ? 1 : 0;
+  // where the samples end: the cap, or the tile edge
+  const float uend = fminf(r.uexit, t_to_u(r, T.ucap));
+  int n = 0, m = 0;
+  const bool umbra = T.prune && best <= -T.tan_rL;  // settled by the descent
+  for (int it = 0; it < (umbra ? 0 : (1 << 24)); ++it) {
+    const float t = step_t(T, n, T.half_delta);
+    if (t > T.ucap) break;
+    const float u = t_to_u(r, t);
+    if (!(u < r.uexit)) break;
+    // texel under sample n (rounding past the edge is clamped)
+    const int ix = min(max((int)floorf((float)r.i + 0.5f + r.Kx * u), 0), T.W - 1);
+    const int iy = min(max((int)floorf((float)r.j + 0.5f + r.Ky * u), 0), T.H - 1);
+    const int cx = ix >> m, cy = iy >> m;
+    bool skip = false;
+    if (T.prune) {
+      n_tst++;
+      const float top = fmaxf(bound_at(T, m, cx, cy) - r.hp, 0.0f);
+      skip = clears(r, T, t, top, need);
+    }
+    if (skip) {
+      // first grid sample at or past the texel's exit (a sample a rounding
+      // error past the exit is still under the bound's half-texel margin)
+      const float ux = ((float)(((cx + ex) << m) - r.i) - 0.5f) * r.invKx;
+      const float uy = ((float)(((cy + ey) << m) - r.j) - 0.5f) * r.invKy;
+      const float tb = u_to_t(r, fminf(fminf(ux, uy), uend));
+      const float nb = ceilf(tb * T.two_over_delta) - 1.0f;
+      n = max(n + 1, (int)fminf(nb, 16777216.0f));
+      m = min(m + 1, mtop);
+    } else if (m > 0) {
+      --m;
+    } else {
+      const Sample s = sample_at(r, T, t, u);
+      n_smp++;
+      float num, den;
+      clearance_terms(r, t, s.dh, num, den);
+      const float key = tangent_key(num, den);
+      if (key < best) {
+        best = key;
+        res.t = t;
+        res.u = u;
+        res.valid = 1;
+        need = need_tangent(T, best);
+        if (T.prune && best <= -T.tan_rL) break;  // umbra: nothing can change s = 0
+      }
+      ++n;
+    }
+  }
+  res.key = best;
+  res.alpha = angle_of(best);
+  return res;
 }

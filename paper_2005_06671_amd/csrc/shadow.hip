@@ -50,10 +50,12 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
     ray_init(T, i, j, hp, r);
     const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
     float alpha;
-    if (MODE == SS_MODE_DP)
+    if (MODE == SS_MODE_EXACT)
+      alpha = shadow_exact(T, r, top, n_lb, n_smp).alpha;
+    else if (MODE == SS_MODE_DP)
       alpha = shadow_dp(T, r, top, n_lb, n_smp).alpha;
     else
-      alpha = shadow_uniform(T, r, top, n_smp);
+      alpha = shadow_uniform(T, r, top, n_smp).alpha;
     out[j * T.W + i] = disc_fraction(alpha, T);
   }
   if (COUNT) {
@@ -63,6 +65,15 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
       if (b) atomicAdd(&counter[1], (unsigned long long)b);
     }
   }
+}
+
+template <bool SPHERE, int MODE>
+__device__ __forceinline__ RayResult forward_of(const TileK& T, const Ray<SPHERE>& r, float hp) {
+  unsigned n_lb = 0, n_smp = 0;
+  const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
+  if (MODE == SS_MODE_EXACT) return shadow_exact(T, r, top, n_lb, n_smp);
+  if (MODE == SS_MODE_DP) return shadow_dp(T, r, top, n_lb, n_smp);
+  return shadow_uniform(T, r, top, n_smp);
 }
 
 // Adjoint: recompute the forward decisions, then apply the chain rule through
@@ -75,7 +86,7 @@ struct SunTrig {
   float se, ce, sa, ca, tan_e;
 };
 
-template <bool SPHERE, int TW>
+template <bool SPHERE, int TW, int MODE>
 __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
                                                       const float* __restrict__ gs,
                                                       float* __restrict__ gh,
@@ -89,9 +100,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
-    const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
-    unsigned n_lb = 0, n_smp = 0;
-    const RayResult res = shadow_dp(T, r, top, n_lb, n_smp);
+    const RayResult res = forward_of<SPHERE, MODE>(T, r, hp);
     const float dd = res.alpha * T.inv_rL;
     if (res.valid && g != 0.0f && fabsf(dd) < 1.0f) {
       const float t = res.t, u = res.u;
@@ -192,7 +201,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
         atomicAdd(&gh[yb * T.W + xb], a_hb * s.fx * s.fy);
       }
       atomicAdd(&gh[j * T.W + i], a_hp);
-      // t = (n + 1) texel / (2 cos e) grows with e; L(e, a) on the unit sphere
+      // t = texel (1/2 + k step) / cos e (every mode) grows with e; L(e, a)
+      // on the unit sphere
       const double dte = (double)a_t * (double)t * (double)st.tan_e;
       ge = dte + (double)a_Lx * (-(double)st.se * st.ca) + (double)a_Ly * (-(double)st.se * st.sa) +
            (double)a_Lz * (double)st.ce;
@@ -239,6 +249,13 @@ static hipError_t launch_fwd_tw(const TileK& T, int mode, bool count, float* out
     else
       hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_DP, false>), grid, block, 0, stream, T,
                          out, counter, nbx, nb);
+  } else if (mode == SS_MODE_EXACT) {
+    if (count)
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_EXACT, true>), grid, block, 0, stream,
+                         T, out, counter, nbx, nb);
+    else
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_EXACT, false>), grid, block, 0,
+                         stream, T, out, counter, nbx, nb);
   } else {
     if (count)
       hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_UNIFORM, true>), grid, block, 0, stream,
@@ -267,8 +284,26 @@ hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, b
                 : launch_fwd_s<false>(T, mode, ray_tile, count, out, counter, stream);
 }
 
-hipError_t launch_adjoint(const TileK& T, bool sphere, double elev, double azim, const float* gs,
-                          float* gh, double* gsun, hipStream_t stream) {
+template <bool SPHERE, int MODE>
+static void adjoint_launch(const TileK& T, const SunTrig& st, const float* gs, float* gh,
+                           double* gsun, int nbx, int nb, hipStream_t stream) {
+  hipLaunchKernelGGL((adjoint_kernel<SPHERE, 8, MODE>), dim3(nb), dim3(256), 0, stream, T, st, gs,
+                     gh, gsun, nbx, nb);
+}
+
+template <bool SPHERE>
+static void adjoint_mode(const TileK& T, int mode, const SunTrig& st, const float* gs, float* gh,
+                         double* gsun, int nbx, int nb, hipStream_t stream) {
+  if (mode == SS_MODE_EXACT)
+    adjoint_launch<SPHERE, SS_MODE_EXACT>(T, st, gs, gh, gsun, nbx, nb, stream);
+  else if (mode == SS_MODE_UNIFORM)
+    adjoint_launch<SPHERE, SS_MODE_UNIFORM>(T, st, gs, gh, gsun, nbx, nb, stream);
+  else
+    adjoint_launch<SPHERE, SS_MODE_DP>(T, st, gs, gh, gsun, nbx, nb, stream);
+}
+
+hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
+                          const float* gs, float* gh, double* gsun, hipStream_t stream) {
   SunTrig st;
   st.se = (float)sin(elev);
   st.ce = (float)cos(elev);
@@ -278,11 +313,10 @@ hipError_t launch_adjoint(const TileK& T, bool sphere, double elev, double azim,
   int nbx, nb;
   grid_for(T, SS_TILE_8x8, &nbx, &nb);
   if (nb == 0) return hipSuccess;
-  dim3 grid(nb), block(256);
   if (sphere)
-    hipLaunchKernelGGL((adjoint_kernel<true, 8>), grid, block, 0, stream, T, st, gs, gh, gsun, nbx, nb);
+    adjoint_mode<true>(T, mode, st, gs, gh, gsun, nbx, nb, stream);
   else
-    hipLaunchKernelGGL((adjoint_kernel<false, 8>), grid, block, 0, stream, T, st, gs, gh, gsun, nbx, nb);
+    adjoint_mode<false>(T, mode, st, gs, gh, gsun, nbx, nb, stream);
   return hipGetLastError();
 }
 

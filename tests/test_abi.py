@@ -96,11 +96,12 @@ def test_rejects_bad_arguments(L):
     p2.n_prime0 = 1
     p2.max_len_m = 1e6
     assert cast(L, t, s, p2) == L.SS_ERR_UNSUPPORTED
-    # backward needs the descent
+    # the exact mode needs the tap-bound pyramid, forward and backward
     _, _, p3 = good(L)
-    p3.mode = 1
+    p3.mode = L.SS_MODE_EXACT
+    assert cast(L, t, s, p3) == L.SS_ERR_INVALID_ARG
     assert lib.ss_shadow_cast_backward(C.byref(t), C.byref(s), C.byref(p3), 0x300000, 0x400000,
-                                       0x500000, None) == L.SS_ERR_UNSUPPORTED
+                                       0x500000, None) == L.SS_ERR_INVALID_ARG
     assert lib.ss_shadow_cast_counted(C.byref(t), C.byref(s), C.byref(p), 0x200000, None,
                                       None) == L.SS_ERR_INVALID_ARG
 
@@ -126,6 +127,29 @@ def test_batched_validation(L):
                                       None) == L.SS_ERR_INVALID_ARG
     assert lib.ss_batched_plan_launch(None, None) == L.SS_ERR_INVALID_ARG
     assert lib.ss_batched_plan_destroy(None) == 0
+    # the exact mode is per tile only
+    outs[4] = 0x600000
+    p.mode = L.SS_MODE_EXACT
+    t.bound = 0x800000
+    tiles = (L.SSTile * 2)(t, t)
+    assert lib.ss_shadow_cast_batched(tiles, 2, suns, 3, C.byref(p), outs, 0x700000, need,
+                                      None) == L.SS_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (5, 3), (100, 37), (4096, 4096), (65536, 3)])
+def test_bound_layout(L, shape):
+    """Tap-bound pyramid: level 0 [rows][width] first, then the maximum-mipmap
+    levels of it at a 64-float aligned base."""
+    lib = L.lib()
+    W, H = shape
+    base = (W * H + 63) // 64 * 64
+    assert lib.ss_bound_level_offset(W, H, 0) == 0
+    for m in range(1, lib.ss_maxmip_levels(W, H)):
+        assert lib.ss_bound_level_offset(W, H, m) == base + lib.ss_maxmip_level_offset(W, H, m)
+    assert lib.ss_bound_floats(W, H) == base + lib.ss_maxmip_floats(W, H)
+    assert lib.ss_bound_floats(0, 5) == -1 and lib.ss_bound_level_offset(W, H, 99) == -1
+    assert lib.ss_bound_build(None, 0, 0, None, None) == 0
+    assert lib.ss_bound_build(None, W, H, 0x100000, None) == L.SS_ERR_INVALID_ARG
 
 
 def test_status_strings(L):

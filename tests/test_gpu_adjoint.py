@@ -56,7 +56,7 @@ def rough(shape, seed, amp):
 def gpu_backward(ss, h, p, g):
     hd = torch.from_numpy(h).to(dev())
     gd = torch.from_numpy(g.astype(np.float32).reshape(h.shape)).to(dev())
-    params = ss.Params(radius_m=p.radius_m, max_len_m=p.max_len_m)
+    params = ss.Params(radius_m=p.radius_m, max_len_m=p.max_len_m, mode=p.mode)
     gh, gsun = ss.shadow_cast_backward(hd, p.texel_m, p.elev, p.azim, gd, p.ang_radius, params)
     torch.cuda.synchronize()
     return gh.cpu().numpy().astype(np.float64), gsun.cpu().numpy()
@@ -66,10 +66,14 @@ CASES = [((256, 256), 20.0, R, 1.5, 0.7, 0.0), ((192, 256), 20.0, math.inf, 2.0,
          ((256, 240), 15.0, R, 1.0, 4.1, 1500.0)]
 
 
+@pytest.mark.parametrize("mode", [0, 2])
 @pytest.mark.parametrize("shape,D,radius,e_deg,az,cap", CASES)
-def test_adjoint_matches_reference_gradient(ss, shape, D, radius, e_deg, az, cap):
+def test_adjoint_matches_reference_gradient(ss, shape, D, radius, e_deg, az, cap, mode):
+    """Descent (mode 0) and exact mode (2): in both the deciding sample sits at
+    t = (n + 1) delta/2, the chain the reference differentiates."""
     h = rough(shape, shape[0] + 3, 80.0)
-    p = oracle.Params(shape[1], shape[0], D, radius, math.radians(e_deg), az, RL, max_len_m=cap)
+    p = oracle.Params(shape[1], shape[0], D, radius, math.radians(e_deg), az, RL, max_len_m=cap,
+                      mode=mode)
     s, _, tr = oracle.shadow(h, p, trace=True)
     mask = well_conditioned(tr)
     inside = (s.reshape(-1) > 0.0) & (s.reshape(-1) < 1.0)
