@@ -215,22 +215,46 @@ def _err_stats(x, ref):
 def leg_accuracy(ss, h, mm, D, suns, c):
     """Image error of the descent and of one-texel uniform stepping against
     dense stepping on the half-texel grid (the grid the descent's final samples
-    use), over every sun of the workload."""
+    use), over every sun of the workload; and the exact mode (the same grid's
+    minimum by branch and bound), timed against dense stepping and checked
+    bit-identical to it."""
     import torch
     from synth import R_MOON
+    W, H = h.shape[1], h.shape[0]
     pd = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"])
     pu1 = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
     pu2 = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM,
                     uniform_step=0.5)
-    dp, u1, u2 = [], [], []
+    px = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_EXACT)
+    bound = ss.bound_build(h)
+    t_bound = _timed(lambda: ss.bound_build(h, out=bound), 3)
+    dp, u1, u2, ex = [], [], [], []
+    t_u2, t_ex, cnt = [], [], []
     for (e, a, r) in suns:
         dp.append(ss.shadow_cast(h, D, e, a, r, pd, mm=mm))
         u1.append(ss.shadow_cast(h, D, e, a, r, pu1, mm=mm))
-        u2.append(ss.shadow_cast(h, D, e, a, r, pu2, mm=mm))
-    dp, u1, u2 = torch.stack(dp), torch.stack(u1), torch.stack(u2)
+        o2 = torch.empty_like(h)
+        ox = torch.empty_like(h)
+        t_u2 += _timed(lambda: ss.shadow_cast(h, D, e, a, r, pu2, mm=mm, out=o2), 1)
+        ss.shadow_cast(h, D, e, a, r, px, mm=mm, out=ox, bound=bound)
+        t_ex += _timed(lambda: ss.shadow_cast(h, D, e, a, r, px, mm=mm, out=ox, bound=bound), 2)[1:]
+        u2.append(o2)
+        ex.append(ox)
+        _, k = ss.shadow_cast_counted(h, D, e, a, r, px, mm=mm, bound=bound)
+        cnt.append([int(v) for v in k.cpu().tolist()])
+    dp, u1, u2, ex = torch.stack(dp), torch.stack(u1), torch.stack(u2), torch.stack(ex)
+    rays = W * H * len(suns)
+    exact = {"mrays_s": rays / (sum(t_ex) / 1e3) / 1e6,
+             "dense_mrays_s": rays / (sum(t_u2) / 1e3) / 1e6,
+             "speedup_vs_dense": sum(t_u2) / sum(t_ex),
+             "bit_identical_to_dense": bool(torch.equal(ex.view(torch.int32), u2.view(torch.int32))),
+             "bound_build_ms": min(t_bound),
+             "tests_per_ray": sum(k[0] for k in cnt) / rays,
+             "samples_per_ray": sum(k[1] for k in cnt) / rays,
+             "launch_ms": t_ex}
     return {"reference": "uniform stepping at delta/2 (dense half-texel grid), all suns",
             "descent": _err_stats(dp, u2), "uniform_1_texel": _err_stats(u1, u2),
-            "mean_s_dense": float(u2.mean())}
+            "mean_s_dense": float(u2.mean())}, exact
 
 
 def leg_cold_maxmip(ss, h, mm, mm_bytes, reps=5):
@@ -324,8 +348,14 @@ def leg_polar(ss, reps=3):
 
     tb = _timed(fwd_bwd, 1)
     n = W * H
+    mean_s = float(out.mean())
+    bound = ss.bound_build(h)
+    px = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_EXACT)
+    tx = _timed(lambda: ss.shadow_cast(h, D, e, a, r, px, mm=mm, out=out, bound=bound), 1)
     res = {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
-           "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "mean_s": float(out.mean())}
+           "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "mean_s": mean_s,
+           "exact_mrays_s": n / (min(tx) / 1e3) / 1e6, "exact_ms": min(tx)}
+    del bound
     del h, mm, out, g, gh
     return res
 
@@ -447,7 +477,7 @@ def main():
 
     extras = {"step_ms_p10_p50_p90": _pct(step_ms), "launch_ms_p10_p50_p90": _pct(launch_ms)}
     if not args.no_extras:
-        extras["accuracy_vs_dense"] = leg_accuracy(ss, h, mm, D, suns, c)
+        extras["accuracy_vs_dense"], extras["exact_mode"] = leg_accuracy(ss, h, mm, D, suns, c)
         maxmip["cold"] = leg_cold_maxmip(ss, h, mm, mm_bytes)
         # uniform stepping, one texel per step, same suns, cap and exits
         pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
