@@ -116,9 +116,16 @@ __device__ __forceinline__ const float* level_ptr(const TileK& T, int m) {
 // outside the level, so this is a memory-safety guard, not a behaviour.
 __device__ __forceinline__ unsigned inside(int v, int n) { return min((unsigned)v, (unsigned)(n - 1)); }
 
+// Row-major index y w + x.  Rows and widths stay below 2^24, so the full-rate
+// 24-bit multiply gives the exact product (the 32-bit one issues at quarter
+// rate).
+__device__ __forceinline__ unsigned idx2(unsigned y, unsigned w, unsigned x) {
+  return __umul24(y, w) + x;
+}
+
 __device__ __forceinline__ float mip_at(const TileK& T, int m, int cx, int cy) {
   const unsigned w = (unsigned)T.lw[m];
-  return level_ptr(T, m)[inside(cy, T.lh[m]) * w + inside(cx, T.lw[m])];
+  return level_ptr(T, m)[idx2(inside(cy, T.lh[m]), w, inside(cx, T.lw[m]))];
 }
 
 // One mip level as a buffer resource: 32-bit offsets, and an offset past the
@@ -137,8 +144,11 @@ __device__ __forceinline__ Level level_of(const TileK& T, int m) {
   return L;
 }
 
+// (A texel outside the level may give any offset; the range check makes the
+// load return 0 or an in-range value, and such candidates are discarded.)
 __device__ __forceinline__ float level_at(const Level& L, int cx, int cy) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(L.rs, (cy * L.w + cx) * 4, 0, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                       L.rs, (int)(idx2((unsigned)cy, (unsigned)L.w, (unsigned)cx) * 4u), 0, 0));
 }
 
 // Lower bound of the clearance over the part [u0, u1] of the ray inside a
@@ -181,8 +191,9 @@ __device__ __forceinline__ Sample sample_at(const Ray<SPHERE>& r, const TileK& T
   const unsigned y0 = (unsigned)min(max(s.y0, 0), T.H - 1), y1 = inside(s.y0 + 1, T.H);
   const float* h = T.h;
   const unsigned W = (unsigned)T.W;
-  const float h00 = h[y0 * W + x0] - r.hp, h10 = h[y0 * W + x1] - r.hp;
-  const float h01 = h[y1 * W + x0] - r.hp, h11 = h[y1 * W + x1] - r.hp;
+  const unsigned r0 = __umul24(y0, W), r1 = __umul24(y1, W);
+  const float h00 = h[r0 + x0] - r.hp, h10 = h[r0 + x1] - r.hp;
+  const float h01 = h[r1 + x0] - r.hp, h11 = h[r1 + x1] - r.hp;
   const float hb = (1.0f - s.fy) * ((1.0f - s.fx) * h00 + s.fx * h10) +
                    s.fy * ((1.0f - s.fx) * h01 + s.fx * h11);
   s.dh = tip_rise(r, T, t) - hb;
@@ -248,17 +259,24 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   // top level: walk the level-m texels crossed for u in [ua, ub]
   int cx = (r.i >> m) + (int)floorf(ldexpf((float)(r.i & (S - 1)) + 0.5f + r.Kx * ua, -m));
   int cy = (r.j >> m) + (int)floorf(ldexpf((float)(r.j & (S - 1)) + 0.5f + r.Ky * ua, -m));
+  // those grid lines relative to the origin texel centre, in texels; they
+  // are half-integers, exact in FP32, and move by +-2^m per step
+  float gx = (float)(((cx + ex) << m) - r.i) - 0.5f;
+  float gy = (float)(((cy + ey) << m) - r.j) - 0.5f;
+  const float stx = (float)(r.sx * S), sty = (float)(r.sy * S);
   const Level Ltop = level_of(T, m);
+  const unsigned lwm = (unsigned)T.lw[m], lhm = (unsigned)T.lh[m];
   float best = SS_INF, bu0 = ua, bu1 = ua, brise = 0.0f;
   int bx = cx, by = cy, have = 0;
   float u0 = ua;
   for (int it = 0; it < 8; ++it) {
-    const float ux = ((float)(((cx + ex) << m) - r.i) - 0.5f) * r.invKx;
-    const float uy = ((float)(((cy + ey) << m) - r.j) - 0.5f) * r.invKy;
+    const float ux = gx * r.invKx;
+    const float uy = gy * r.invKy;
     const float u1 = fminf(fminf(ux, uy), ub);
     // a piece in a texel outside the level is a rounding sliver at the tile edge
-    const bool ok = u1 > u0 && (unsigned)cx < (unsigned)T.lw[m] && (unsigned)cy < (unsigned)T.lh[m];
-    const float uc = fminf(fmaxf(r.uhmin, u0), u1);
+    const bool ok = u1 > u0 && (unsigned)cx < lwm && (unsigned)cy < lhm;
+    // where the tip is lowest on [u0, u1] (a piece that is not ok is discarded)
+    const float uc = __builtin_amdgcn_fmed3f(r.uhmin, u0, u1);
     const float rise = tip_rise(r, T, u_to_t(r, uc));
     const float lb = rise - (level_at(Ltop, cx, cy) - r.hp);
     n_lb += ok ? 1u : 0u;
@@ -272,27 +290,39 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     have |= take ? 1 : 0;
     u0 = fmaxf(u0, u1);
     if (!(u1 < ub)) break;
-    cx += ux <= uy ? r.sx : 0;
-    cy += uy <= ux ? r.sy : 0;
+    const bool mx = ux <= uy, my = uy <= ux;
+    cx += mx ? r.sx : 0;
+    gx += mx ? stx : 0.0f;
+    cy += my ? r.sy : 0;
+    gy += my ? sty : 0.0f;
   }
   if (!have) return;
-  // descend: the children of the chosen texel crossed by the ray, split at the
-  // parent's two mid-lines into at most three pieces
+  // descend: the children of the chosen texel crossed by the ray.  The
+  // parent's two mid-lines split its stretch [bu0, bu1] into at most three
+  // pieces, in order: before both crossings, after the first, after both.  The
+  // child before a mid-line (in the direction of travel) is the low one when
+  // moving forward or not at all; each crossing flips that axis, so the
+  // children follow from which mid-line comes first.  A crossing outside the
+  // stretch (an infinite one on an axis the path does not move along, too)
+  // leaves its piece empty.
+  const int bfx = 1 - ex, bfy = 1 - ey;  // child bits before the mid-lines
+  // parent's low edge relative to the origin texel centre, in texels
+  float fx = (float)((bx << m) - r.i) - 0.5f;
+  float fy = (float)((by << m) - r.j) - 0.5f;
   for (int lv = m; lv > 0; --lv) {
     const int half = 1 << (lv - 1);
+    const float fh = (float)half;
     const Level Lc = level_of(T, lv - 1);
     const int px = 2 * bx, py = 2 * by;
-    const float mxr = (float)((px + 1) * half - r.i) - 0.5f;
-    const float myr = (float)((py + 1) * half - r.j) - 0.5f;
+    const float mxr = fx + fh, myr = fy + fh;  // mid-lines (exact)
     const float umx = mxr * r.invKx, umy = myr * r.invKy;
-    const float c1 = fminf(fmaxf(fminf(umx, umy), bu0), bu1);
-    const float c2 = fminf(fmaxf(fmaxf(umx, umy), bu0), bu1);
-    // child texel of each piece from its midpoint
-    const float m0 = 0.5f * (bu0 + c1), m1 = 0.5f * (c1 + c2), m2 = 0.5f * (c2 + bu1);
-    const int x0 = px + (r.Kx * m0 >= mxr ? 1 : 0), y0 = py + (r.Ky * m0 >= myr ? 1 : 0);
-    const int x1 = px + (r.Kx * m1 >= mxr ? 1 : 0), y1 = py + (r.Ky * m1 >= myr ? 1 : 0);
-    const int x2 = px + (r.Kx * m2 >= mxr ? 1 : 0), y2 = py + (r.Ky * m2 >= myr ? 1 : 0);
-    const float M0 = level_at(Lc, x0, y0), M1 = level_at(Lc, x1, y1), M2 = level_at(Lc, x2, y2);
+    const bool xfirst = umx <= umy;
+    const float c1 = __builtin_amdgcn_fmed3f(fminf(umx, umy), bu0, bu1);
+    const float c2 = __builtin_amdgcn_fmed3f(fmaxf(umx, umy), bu0, bu1);
+    const int xa = px + bfx, ya = py + bfy;  // before both
+    const int xc = px + ex, yc = py + ey;    // after both
+    const int xb = xfirst ? xc : xa, yb = xfirst ? ya : yc;
+    const float M0 = level_at(Lc, xa, ya), M1 = level_at(Lc, xb, yb), M2 = level_at(Lc, xc, yc);
     // tip rise at each piece's entry: the first piece enters where the parent
     // did (already known); identical to evaluating it again
     float r0, r1, r2;
@@ -305,11 +335,11 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
       r1 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c1), c2)));
       r2 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c2), bu1)));
     }
-    // children beyond a ragged edge are absent
+    // children beyond a ragged edge are absent (only px + 1 or py + 1 can be)
     const int cw = T.lw[lv - 1], ch = T.lh[lv - 1];
-    const bool ok0 = c1 > bu0 && x0 < cw && y0 < ch;
-    const bool ok1 = c2 > c1 && x1 < cw && y1 < ch;
-    const bool ok2 = bu1 > c2 && x2 < cw && y2 < ch;
+    const bool ok0 = c1 > bu0 && xa < cw && ya < ch;
+    const bool ok1 = c2 > c1 && xb < cw && yb < ch;
+    const bool ok2 = bu1 > c2 && xc < cw && yc < ch;
     const float lb0 = ok0 ? r0 - (M0 - r.hp) : SS_INF;
     const float lb1 = ok1 ? r1 - (M1 - r.hp) : SS_INF;
     const float lb2 = ok2 ? r2 - (M2 - r.hp) : SS_INF;
@@ -320,8 +350,12 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     if (ok1 && (k < 0 || lb1 <= bl)) { k = 1; bl = lb1; }
     if (ok2 && (k < 0 || lb2 <= bl)) { k = 2; bl = lb2; }
     if (k < 0) return;
-    bx = k == 0 ? x0 : (k == 1 ? x1 : x2);
-    by = k == 0 ? y0 : (k == 1 ? y1 : y2);
+    const int nx = k == 0 ? xa : (k == 1 ? xb : xc);
+    const int ny = k == 0 ? ya : (k == 1 ? yb : yc);
+    fx = nx != px ? mxr : fx;
+    fy = ny != py ? myr : fy;
+    bx = nx;
+    by = ny;
     brise = k == 0 ? r0 : (k == 1 ? r1 : r2);
     const float nu0 = k == 0 ? bu0 : (k == 1 ? c1 : c2);
     const float nu1 = k == 0 ? c1 : (k == 1 ? c2 : bu1);
@@ -505,7 +539,7 @@ __device__ __forceinline__ RayResult shadow_uniform(const TileK& T, const Ray<SP
 __device__ __forceinline__ float bound_at(const TileK& T, int m, int cx, int cy) {
   const float* base = m == 0 ? T.bnd : T.bmm + T.loff[m];
   const int w = (T.W + (1 << m) - 1) >> m;
-  return base[cy * w + cx];
+  return base[idx2((unsigned)cy, (unsigned)w, (unsigned)cx)];
 }
 
 // Exact mode: the smallest clearance over every sample of the grid
