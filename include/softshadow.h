@@ -7,6 +7,8 @@
  *  - Heights are float32, row-major [rows][width], metres above a reference
  *    sphere of radius body_radius_m.  Texel (column i, row j) covers
  *    [i, i+1) x [j, j+1) in texel units and its centre is a ray origin.
+ *    Sizes: width, rows <= 65536 and width * rows < 2^30 (otherwise
+ *    SS_ERR_INVALID_ARG, or -1 / 0 from the layout functions).
  *  - The tile is a gnomonic patch: the tile-centre frame has z along the local
  *    vertical, x along +column, y along +row; the texel grid lies on the plane
  *    tangent to the sphere at the tile centre and spacing texel_m is measured

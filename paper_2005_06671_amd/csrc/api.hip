@@ -48,8 +48,11 @@ static void dims_of(int32_t W, int32_t H, int m, int* w, int* h) {
   *h = (int)b;
 }
 
+// Each side at most 65536 and fewer than 2^30 texels: the kernels address a
+// level through a buffer resource whose size and offsets are 32-bit byte
+// counts.
 static bool size_ok(int32_t W, int32_t H) {
-  return W >= 1 && H >= 1 && W <= 65536 && H <= 65536 && (int64_t)W * H <= 2147483647LL;
+  return W >= 1 && H >= 1 && W <= 65536 && H <= 65536 && (int64_t)W * H < (1LL << 30);
 }
 
 extern "C" int32_t ss_maxmip_levels(int32_t width, int32_t rows) {

@@ -136,6 +136,19 @@ def test_batched_validation(L):
                                       None) == L.SS_ERR_UNSUPPORTED
 
 
+def test_size_limits(L):
+    """Each side <= 65536 and fewer than 2^30 texels (32-bit byte offsets)."""
+    lib = L.lib()
+    assert lib.ss_maxmip_levels(65536, 16383) == 17
+    assert lib.ss_maxmip_levels(32768, 32768) == 0
+    assert lib.ss_maxmip_floats(65536, 16384) == -1
+    assert lib.ss_bound_floats(65537, 1) == -1
+    t, s, p = good(L)
+    t.width, t.rows = 32768, 32768
+    assert cast(L, t, s, p) == L.SS_ERR_INVALID_ARG
+    assert lib.ss_maxmip_build(0x100000, 32768, 32768, 0x200000, 0, None) == L.SS_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (1, 7), (5, 3), (100, 37), (4096, 4096), (65536, 3)])
 def test_bound_layout(L, shape):
     """Tap-bound pyramid: level 0 [rows][width] first, then the maximum-mipmap
