@@ -151,24 +151,6 @@ __device__ __forceinline__ float level_at(const Level& L, int cx, int cy) {
                                        L.rs, (int)(idx2((unsigned)cy, (unsigned)L.w, (unsigned)cx) * 4u), 0, 0));
 }
 
-// Lower bound of the clearance over the part [u0, u1] of the ray inside a
-// level-m texel: smallest tip height there minus the texel's maximum height
-// (Sec. 3.2, Eq. 4 with the maximum mipmap), relative to h_p.
-template <bool SPHERE>
-__device__ __forceinline__ float lower_bound(const Ray<SPHERE>& r, const TileK& T, int m, int cx,
-                                             int cy, float u0, float u1) {
-  const float uc = fminf(fmaxf(r.uhmin, u0), u1);
-  const float t = u_to_t(r, uc);
-  return tip_rise(r, T, t) - (mip_at(T, m, cx, cy) - r.hp);
-}
-
-// The same bound when the tip rise at the texel's entry is already known (the
-// tip height rises from the start, so the entry is where it is smallest).
-__device__ __forceinline__ float lower_bound_at(const TileK& T, float rise, int m, int cx, int cy,
-                                                float hp) {
-  return rise - (mip_at(T, m, cx, cy) - hp);
-}
-
 // Bilinear sample of the terrain below the ray tip at ray length t (u = u(t)):
 // clearance height and the tap layout (for the adjoint).
 struct Sample {
@@ -189,11 +171,9 @@ __device__ __forceinline__ Sample sample_at(const Ray<SPHERE>& r, const TileK& T
   // clamp to the edge (the tap index is -1 only left of the first centre)
   const unsigned x0 = (unsigned)min(max(s.x0, 0), T.W - 1), x1 = inside(s.x0 + 1, T.W);
   const unsigned y0 = (unsigned)min(max(s.y0, 0), T.H - 1), y1 = inside(s.y0 + 1, T.H);
-  const float* h = T.h;
-  const unsigned W = (unsigned)T.W;
-  const unsigned r0 = __umul24(y0, W), r1 = __umul24(y1, W);
-  const float h00 = h[r0 + x0] - r.hp, h10 = h[r0 + x1] - r.hp;
-  const float h01 = h[r1 + x0] - r.hp, h11 = h[r1 + x1] - r.hp;
+  const Level L0 = level_of(T, 0);
+  const float h00 = level_at(L0, x0, y0) - r.hp, h10 = level_at(L0, x1, y0) - r.hp;
+  const float h01 = level_at(L0, x0, y1) - r.hp, h11 = level_at(L0, x1, y1) - r.hp;
   const float hb = (1.0f - s.fy) * ((1.0f - s.fx) * h00 + s.fx * h10) +
                    s.fy * ((1.0f - s.fx) * h01 + s.fx * h11);
   s.dh = tip_rise(r, T, t) - hb;
@@ -277,6 +257,8 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     const bool ok = u1 > u0 && (unsigned)cx < lwm && (unsigned)cy < lhm;
     // where the tip is lowest on [u0, u1] (a piece that is not ok is discarded)
     const float uc = __builtin_amdgcn_fmed3f(r.uhmin, u0, u1);
+    // lower bound of the clearance over the piece: lowest tip height minus
+    // the texel's maximum height (Sec. 3.2, Eq. 4 with the maximum mipmap)
     const float rise = tip_rise(r, T, u_to_t(r, uc));
     const float lb = rise - (level_at(Ltop, cx, cy) - r.hp);
     n_lb += ok ? 1u : 0u;
@@ -335,30 +317,34 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
       r1 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c1), c2)));
       r2 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c2), bu1)));
     }
-    // children beyond a ragged edge are absent (only px + 1 or py + 1 can be)
-    const int cw = T.lw[lv - 1], ch = T.lh[lv - 1];
-    const bool ok0 = c1 > bu0 && xa < cw && ya < ch;
-    const bool ok1 = c2 > c1 && xb < cw && yb < ch;
-    const bool ok2 = bu1 > c2 && xc < cw && yc < ch;
+    // children beyond a ragged edge are absent; px and py always exist, so
+    // only the high children px + 1, py + 1 can be missing
+    const bool hx = px + 1 < T.lw[lv - 1], hy = py + 1 < T.lh[lv - 1];
+    const bool ina = (ex == 1 || hx) && (ey == 1 || hy);  // before both
+    const bool inc = (ex == 0 || hx) && (ey == 0 || hy);  // after both
+    const bool inb = xfirst ? ((ex == 0 || hx) && (ey == 1 || hy)) : ((ex == 1 || hx) && (ey == 0 || hy));
+    const bool ok0 = c1 > bu0 && ina;
+    const bool ok1 = c2 > c1 && inb;
+    const bool ok2 = bu1 > c2 && inc;
+    // an absent piece has bound +inf; present ones are finite
     const float lb0 = ok0 ? r0 - (M0 - r.hp) : SS_INF;
     const float lb1 = ok1 ? r1 - (M1 - r.hp) : SS_INF;
     const float lb2 = ok2 ? r2 - (M2 - r.hp) : SS_INF;
     n_lb += (ok0 ? 1u : 0u) + (ok1 ? 1u : 0u) + (ok2 ? 1u : 0u);
     // strict argmin from the far end == '<=' from the near end
-    int k = ok0 ? 0 : -1;
-    float bl = lb0;
-    if (ok1 && (k < 0 || lb1 <= bl)) { k = 1; bl = lb1; }
-    if (ok2 && (k < 0 || lb2 <= bl)) { k = 2; bl = lb2; }
-    if (k < 0) return;
-    const int nx = k == 0 ? xa : (k == 1 ? xb : xc);
-    const int ny = k == 0 ? ya : (k == 1 ? yb : yc);
+    const bool t1 = lb1 <= lb0;
+    const float b01 = t1 ? lb1 : lb0;
+    const bool t2 = lb2 <= b01;
+    if (!((t2 ? lb2 : b01) < SS_INF)) return;  // no piece inside the level
+    const int nx = t2 ? xc : (t1 ? xb : xa);
+    const int ny = t2 ? yc : (t1 ? yb : ya);
     fx = nx != px ? mxr : fx;
     fy = ny != py ? myr : fy;
     bx = nx;
     by = ny;
-    brise = k == 0 ? r0 : (k == 1 ? r1 : r2);
-    const float nu0 = k == 0 ? bu0 : (k == 1 ? c1 : c2);
-    const float nu1 = k == 0 ? c1 : (k == 1 ? c2 : bu1);
+    brise = t2 ? r2 : (t1 ? r1 : r0);
+    const float nu0 = t2 ? c2 : (t1 ? c1 : bu0);
+    const float nu1 = t2 ? bu1 : (t1 ? c2 : c1);
     bu0 = nu0;
     bu1 = nu1;
   }
@@ -415,35 +401,6 @@ __device__ __forceinline__ float need_tangent(const TileK& T, float key) {
   return (k + T.tan_margin) * ss_rcp(1.0f - k * T.tan_margin);
 }
 
-// Highest terrain (relative to h_p, at least 0) that any bilinear tap of run
-// j's final samples can touch: the samples lie on the ray for t in
-// [tlo, tau_{j+1} + 3 delta/4] inside the tile, and a sample at texture point q
-// reads taps within [q - 3/2, q + 1/2] per axis.  That box spans at most two
-// texels per axis of level max(m0 + 1, 3), whose maxima bound it.
-template <bool SPHERE>
-__device__ __forceinline__ float run_top(const TileK& T, const Ray<SPHERE>& r, int j, float tlo) {
-  const int mb = max(T.m0[j] + 1, 3);
-  if (mb >= T.L) return fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp;
-  const float ulo = t_to_u(r, tlo);
-  const float uhi = fminf(t_to_u(r, T.tau[j + 1] + 1.5f * T.half_delta), r.uexit);
-  const float xa = r.Kx * ulo, xb = r.Kx * uhi, ya = r.Ky * ulo, yb = r.Ky * uhi;
-  // FP32 slack on the offsets (relative ~1e-6) plus a hundredth of a texel
-  const float sx = 0.01f + 1e-5f * fmaxf(fabsf(xa), fabsf(xb));
-  const float sy = 0.01f + 1e-5f * fmaxf(fabsf(ya), fabsf(yb));
-  const float x0 = (float)r.i + 0.5f + fminf(xa, xb) - 1.5f - sx;
-  const float x1 = (float)r.i + 0.5f + fmaxf(xa, xb) + 0.5f + sx;
-  const float y0 = (float)r.j + 0.5f + fminf(ya, yb) - 1.5f - sy;
-  const float y1 = (float)r.j + 0.5f + fmaxf(ya, yb) + 0.5f + sy;
-  const int ix0 = min(max((int)floorf(x0), 0), T.W - 1) >> mb;
-  const int ix1 = min(max((int)floorf(x1), 0), T.W - 1) >> mb;
-  const int iy0 = min(max((int)floorf(y0), 0), T.H - 1) >> mb;
-  const int iy1 = min(max((int)floorf(y1), 0), T.H - 1) >> mb;
-  if (ix1 > ix0 + 1 || iy1 > iy0 + 1) return fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp;
-  const float m = fmaxf(fmaxf(mip_at(T, mb, ix0, iy0), mip_at(T, mb, ix1, iy0)),
-                        fmaxf(mip_at(T, mb, ix0, iy1), mip_at(T, mb, ix1, iy1)));
-  return fmaxf(m, r.hp) - r.hp;
-}
-
 struct RayResult {
   float alpha;
   float key;      // tangent key of alpha (orders like alpha)
@@ -471,8 +428,7 @@ __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>
     if (T.prune) {
       // every final sample of run j lies at t >= tau_j - 3 delta/4
       const float tlo = fmaxf(T.half_delta, ta - 1.5f * T.half_delta);
-      if (clears(r, T, tlo, top, need)) break;                     // nothing ahead is high enough
-      if (clears(r, T, tlo, run_top(T, r, j, tlo), need)) continue;  // nor in this run
+      if (clears(r, T, tlo, top, need)) break;  // nothing ahead is high enough
     }
     SegOut so;
     descend_run(T, r, j, so, n_lb, n_smp);
