@@ -27,6 +27,7 @@ struct Ray {
   float invKx, invKy;
   float c;           // projective constant: u = t / (1 + c t)
   float sp, cp;      // n.L and |n x L| at the origin (radial normal n)
+  float sp2;         // 2 sp
   float invrho;      // 1 / |p|
   float uexit;       // u where the path leaves the tile
   float uhmin;       // u where the tip height is smallest (-inf: rising from the start)
@@ -71,6 +72,7 @@ __device__ __forceinline__ void ray_init(const TileK& T, int i, int j, float hp,
     r.invrho = 0.0f;
     r.uhmin = T.Lz >= 0.0f ? -SS_INF : SS_INF;
   }
+  r.sp2 = 2.0f * r.sp;
   r.sx = r.Kx > 0.0f ? 1 : (r.Kx < 0.0f ? -1 : 0);
   r.sy = r.Ky > 0.0f ? 1 : (r.Ky < 0.0f ? -1 : 0);
   // +inf on an axis the path never moves along: every crossing time on it is
@@ -105,6 +107,22 @@ __device__ __forceinline__ float tip_rise(const Ray<SPHERE>& r, const TileK& T, 
     return t * q * ss_rcp(ss_sqrt(1.0f + x * q) + 1.0f);
   }
   return t * T.Lz;
+}
+
+// The same tip height at the texture parameter u (t = u / A, A = 1 - c u):
+// |p + t L| - |p| = u P / ((S + A) A) with P = 2 s A + u/rho and
+// S = sqrt(A^2 + (u/rho) P), still free of cancellation; one reciprocal
+// fewer than converting u to t first.
+template <bool SPHERE>
+__device__ __forceinline__ float tip_rise_u(const Ray<SPHERE>& r, const TileK& T, float u) {
+  if (SPHERE) {
+    const float A = fmaf(-r.c, u, 1.0f);
+    const float v = u * r.invrho;
+    const float P = fmaf(r.sp2, A, v);
+    const float S = ss_sqrt(fmaf(A, A, v * P));
+    return u * P * ss_rcp((S + A) * A);
+  }
+  return u * T.Lz;
 }
 
 __device__ __forceinline__ const float* level_ptr(const TileK& T, int m) {
@@ -259,7 +277,7 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     const float uc = __builtin_amdgcn_fmed3f(r.uhmin, u0, u1);
     // lower bound of the clearance over the piece: lowest tip height minus
     // the texel's maximum height (Sec. 3.2, Eq. 4 with the maximum mipmap)
-    const float rise = tip_rise(r, T, u_to_t(r, uc));
+    const float rise = tip_rise_u(r, T, uc);
     const float lb = rise - (level_at(Ltop, cx, cy) - r.hp);
     n_lb += ok ? 1u : 0u;
     const bool take = ok && lb <= best;
@@ -310,12 +328,12 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
     float r0, r1, r2;
     if (rising) {
       r0 = brise;
-      r1 = tip_rise(r, T, u_to_t(r, c1));
-      r2 = tip_rise(r, T, u_to_t(r, c2));
+      r1 = tip_rise_u(r, T, c1);
+      r2 = tip_rise_u(r, T, c2);
     } else {
-      r0 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, bu0), c1)));
-      r1 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c1), c2)));
-      r2 = tip_rise(r, T, u_to_t(r, fminf(fmaxf(r.uhmin, c2), bu1)));
+      r0 = tip_rise_u(r, T, fminf(fmaxf(r.uhmin, bu0), c1));
+      r1 = tip_rise_u(r, T, fminf(fmaxf(r.uhmin, c1), c2));
+      r2 = tip_rise_u(r, T, fminf(fmaxf(r.uhmin, c2), bu1));
     }
     // children beyond a ragged edge are absent; px and py always exist, so
     // only the high children px + 1, py + 1 can be missing
