@@ -34,7 +34,7 @@ class _Params(C.Structure):
                 ("ang_radius_rad", C.c_double), ("max_len_m", C.c_double),
                 ("n_prime0", C.c_int32), ("schedule", C.c_int32), ("n_segments", C.c_int32),
                 ("mode", C.c_int32), ("uniform_step", C.c_double),
-                ("uniform_tmax_m", C.c_double)]
+                ("uniform_tmax_m", C.c_double), ("n_prime_list", C.c_int32 * 16)]
 
 
 TRACE_DTYPE = np.dtype([("seg", np.int32), ("n", np.int32), ("t", np.float64),
@@ -106,11 +106,13 @@ class Params:
     mode: int = 0
     uniform_step: float = 1.0
     uniform_tmax_m: float = 0.0
+    n_prime_list: tuple = ()
 
     def c(self) -> _Params:
+        lst = (C.c_int32 * 16)(*[int(v) for v in self.n_prime_list][:16])
         return _Params(self.width, self.rows, self.texel_m, self.radius_m, self.elev, self.azim,
                        self.ang_radius, self.max_len_m, self.n_prime0, self.schedule,
-                       self.n_segments, self.mode, self.uniform_step, self.uniform_tmax_m)
+                       self.n_segments, self.mode, self.uniform_step, self.uniform_tmax_m, lst)
 
     def replace(self, **kw) -> "Params":
         d = dict(self.__dict__)

@@ -149,6 +149,7 @@ void or_setup(setup_t* s, const or_ctx* c, const or_params* p) {
   int j = 0;
   for (;;) {
     int np = p->schedule == 1 ? p->n_prime0 : p->n_prime0 + j;
+    if (p->schedule == 2) np = p->n_prime_list[j < 16 ? j : 15];
     if (np > L) np = L;
     if (np < 1) np = 1;
     s->m0[j] = np - 1;
@@ -479,7 +480,85 @@ static void dp_segment(const ray_t* r, int jseg, seg_result* out) {
   out->alpha = or_alpha_of(r, out->t, out->dh);
 }
 
-static double shadow_dp(const ray_t* r, or_trace* tr) {
+/* Alg. 1 read literally: the point-sample variant of the descent.  Positions
+ * along run j are indices n on the half-texel grid t_n = tau0 + n delta/2; the
+ * algorithm's normalised t in [0, 1] is (n - a_j) / 2^(m0+1), a_j the run's
+ * first index.  Level k (mip m = m0 - k) reads the maximum mipmap at the texel
+ * holding the ray tip at n = a_j + K, a_j + K - 2^m, a_j + K - 2^(m+1), in that
+ * order (the far one first, so strict '<' keeps it on a tie); the smallest
+ * H - max h gives K*, and the next level starts at K* + 2^m.  K starts at
+ * 2^(m0+1) (t = 1).  The last level (m = 0) samples the heightfield
+ * bilinearly, and the chosen sample's exact angle is the run's clearance, as
+ * in the texel descent.  A level with no sample inside the tile ends the run. */
+static void point_segment(const ray_t* r, int jseg, seg_result* out) {
+  const setup_t* s = r->s;
+  const or_ctx* c = s->c;
+  out->alpha = INFINITY;
+  out->n = -1;
+  out->base_i = out->base_j = -1;
+  out->evals = 0;
+  const int m0 = s->m0[jseg];
+  long a = 0;
+  for (int i = 0; i < jseg; ++i) a += 2L << s->m0[i];
+  long K = 2L << m0;
+  for (int m = m0; m >= 0; --m) {
+    const long step = 1L << m;
+    double best = INFINITY, second = INFINITY;
+    long kstar = -1;
+    double bqx = 0.0, bqy = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      long n = a + K - i * step;
+      double t = or_t_grid(s, n);
+      double qx, qy, Ht;
+      or_ray_point(r, t, &qx, &qy, &Ht);
+      /* where a rounding of q could change the texel read or the tile test */
+      double fx = ldexp(qx, -m) - floor(ldexp(qx, -m)), fy = ldexp(qy, -m) - floor(ldexp(qy, -m));
+      double g = fmin(fmin(fx, 1.0 - fx), fmin(fy, 1.0 - fy)) * ldexp(1.0, m);
+      g = fmin(g, fmin(fmin(fabs(qx), fabs(qx - s->p->width)), fmin(fabs(qy), fabs(qy - s->p->rows))));
+      g /= 1.0 + t / s->delta;
+      if (m > 0 && g < out->margin_geo) out->margin_geo = g;
+      if (!or_inside(s, qx, qy)) continue;
+      double v;
+      if (m > 0) {
+        int cx = (int)floor(ldexp(qx, -m)), cy = (int)floor(ldexp(qy, -m));
+        v = Ht - c->level[m][(int64_t)cy * c->w[m] + cx];
+      } else {
+        v = Ht - or_bilinear(s, qx, qy);
+      }
+      out->evals++;
+      if (v < best) {
+        second = best;
+        best = v;
+        kstar = K - i * step;
+        bqx = qx;
+        bqy = qy;
+      } else if (v < second) {
+        second = v;
+      }
+    }
+    if (kstar < 0) return;
+    if (m > 0) {
+      if (second - best < out->margin_lb) out->margin_lb = second - best;
+      K = kstar + step;
+      continue;
+    }
+    if (second - best < out->margin_dh) out->margin_dh = second - best;
+    out->n = a + kstar;
+    out->t = or_t_grid(s, out->n);
+    out->dh = best;
+    out->alpha = or_alpha_of(r, out->t, best);
+    out->base_i = (int)floor(bqx);
+    out->base_j = (int)floor(bqy);
+  }
+}
+
+typedef void (*segment_fn)(const ray_t* r, int jseg, seg_result* out);
+
+static double shadow_runs(const ray_t* r, segment_fn segment, or_trace* tr);
+
+static double shadow_dp(const ray_t* r, or_trace* tr) { return shadow_runs(r, dp_segment, tr); }
+
+static double shadow_runs(const ray_t* r, segment_fn segment, or_trace* tr) {
   const setup_t* s = r->s;
   double alpha = INFINITY, second = INFINITY;
   or_trace t0;
@@ -492,7 +571,7 @@ static double shadow_dp(const ray_t* r, or_trace* tr) {
   for (int j = 0; j < s->nseg; ++j) {
     seg_result sr;
     sr.margin_lb = sr.margin_dh = sr.margin_round = sr.margin_geo = INFINITY;
-    dp_segment(r, j, &sr);
+    segment(r, j, &sr);
     t0.evals += sr.evals;
     if (sr.margin_lb < t0.margin_lb) t0.margin_lb = sr.margin_lb;
     if (sr.margin_dh < t0.margin_dh) t0.margin_dh = sr.margin_dh;
@@ -595,6 +674,8 @@ int32_t or_shadow(const or_ctx* c, const or_params* p, const int64_t* rays, int6
       alpha = shadow_uniform(&r, p->uniform_step * s.delta, &tr);
     else if (p->mode == 2)
       alpha = shadow_uniform(&r, 0.5 * s.delta, &tr);
+    else if (p->mode == 3)
+      alpha = shadow_runs(&r, point_segment, &tr);
     else
       alpha = shadow_dp(&r, &tr);
     double sv = 1.0;

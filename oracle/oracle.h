@@ -31,12 +31,15 @@ typedef struct {
   double ang_radius_rad;  /* apparent radius of the sun disc */
   double max_len_m;       /* horizontal ray cap; <= 0: rays run to the tile edge */
   int32_t n_prime0;       /* mip levels traced by the first segment */
-  int32_t schedule;       /* 0: N'_j = N'_0 + j (geometric); 1: N'_j = N'_0 (equal) */
+  int32_t schedule;       /* 0: N'_j = N'_0 + j (geometric); 1: N'_j = N'_0 (equal);
+                             2: N'_j = n_prime_list[j] for n_segments runs */
   int32_t n_segments;     /* > 0 overrides the segment count derived from the cap */
   int32_t mode;           /* 0: dynamic-programming descent; 1: uniform stepping;
-                             2: exact minimum over the half-texel grid (dense stepping) */
+                             2: exact minimum over the half-texel grid (dense stepping);
+                             3: Alg. 1's point-sample descent */
   double uniform_step;    /* uniform step, texels of horizontal travel */
   double uniform_tmax_m;  /* > 0 overrides the uniform cap on ray length t */
+  int32_t n_prime_list[16]; /* schedule 2: levels of each run */
 } or_params;
 
 typedef struct {

@@ -38,7 +38,7 @@ def fbm_like(shape, seed, amp):
 
 @pytest.mark.parametrize("radius,elev", [(math.inf, RL * 1.001), (math.inf, math.radians(3)),
                                          (R, math.radians(0.3)), (R, math.radians(2.0))])
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_flat_ground_is_lit(orc, radius, elev, mode):
     h = np.zeros((64, 64), np.float32)
     for a in (0.0, 0.7, 2.5, 4.0):
@@ -47,7 +47,7 @@ def test_flat_ground_is_lit(orc, radius, elev, mode):
         assert np.all(s == 1.0)
 
 
-@pytest.mark.parametrize("mode,step", [(0, 1.0), (1, 1.0), (1, 0.5), (2, 1.0)])
+@pytest.mark.parametrize("mode,step", [(0, 1.0), (1, 1.0), (1, 0.5), (2, 1.0), (3, 1.0)])
 def test_half_set_sun(orc, mode, step):
     """Plane, h = 0, e = 0.2 deg < r_L: every sample's clearance is exactly e."""
     e = math.radians(0.2)
