@@ -45,9 +45,13 @@ extern "C" {
 #define SS_MODE_EXACT 2          /* exact minimum over the half-texel sample grid of Alg. 1's
                                     final samples, by branch and bound over the tap-bound
                                     pyramid (Sec. 2: global minimisation) */
+#define SS_MODE_POINT 3          /* Alg. 1 read literally: three point samples of the max-mip
+                                    per level at fixed offsets behind the previous choice */
 
 #define SS_SCHED_GEOMETRIC 0     /* segment j traces N'_0 + j levels (capped at the mipmap) */
 #define SS_SCHED_EQUAL 1         /* every segment traces N'_0 levels (the paper's {5,5,5}) */
+#define SS_SCHED_LIST 2          /* segment j traces n_prime_list[j] levels, n_segments of them
+                                    (1..16; the paper's {5,5,5,3}, Sec. 6.3) */
 
 /* Sun direction in the tile-centre frame (Sec. 3.1: shadow ray toward the disc
  * centre; Sec. 3.4: apparent disc radius r_L).  |elev_rad| < pi/2; azimuth is
@@ -69,6 +73,7 @@ typedef struct {
   double uniform_step;     /* SS_MODE_UNIFORM: step in texels of horizontal travel, >= 1/64 (0 -> 1) */
   int32_t prune;           /* 1: skip work that cannot change the result (bitwise-identical) */
   int32_t ray_tile;        /* ray-tile shape code, 0 = default (results never depend on it) */
+  int32_t n_prime_list[16];/* SS_SCHED_LIST: levels per segment, each >= 1 */
 } ss_params;
 
 /* One heightfield tile.  `maxmip` holds levels >= 1 of its maximum mipmap in
@@ -129,7 +134,12 @@ int32_t ss_bound_build(const float* d_height, int32_t width, int32_t rows, float
  * and write the visible fraction of the sun disc (Sec. 3.4, Eq. 6 circular
  * segment) to d_shadow[j*width + i] in [0, 1] (1 = fully lit).  Overwrites
  * d_shadow.  tile->maxmip must hold the built mipmap of tile->height, and in
- * SS_MODE_EXACT tile->bound its tap-bound pyramid (NULL: SS_ERR_INVALID_ARG). */
+ * SS_MODE_EXACT tile->bound its tap-bound pyramid (NULL: SS_ERR_INVALID_ARG).
+ * SS_MODE_POINT runs Alg. 1's point-sample descent on the same segments:
+ * level k of a segment of N' levels reads the maximum mipmap (level N'-1-k,
+ * nearest texel) under the ray tip at three grid samples 2^(N'-1-k) half
+ * texels apart ending at the previous choice plus that spacing, the last level
+ * reads the heightfield bilinearly, and the chosen sample's clearance counts. */
 int32_t ss_shadow_cast(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                        float* d_shadow, void* stream);
 
@@ -159,7 +169,7 @@ int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns);
  * k in one persistent launch that takes (tile, sun, ray block) items from a
  * queue in d_workspace.  Outputs are bit-identical to ss_shadow_cast with the
  * same parameters.  d_workspace is used for the duration of the call.
- * SS_MODE_DP and SS_MODE_UNIFORM (SS_MODE_EXACT: SS_ERR_UNSUPPORTED). */
+ * SS_MODE_DP, SS_MODE_UNIFORM and SS_MODE_POINT (SS_MODE_EXACT: SS_ERR_UNSUPPORTED). */
 int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
                                int32_t n_suns, const ss_params* params, float* const* d_shadow,
                                void* d_workspace, int64_t workspace_bytes, void* stream);

@@ -9,5 +9,5 @@ from .api import (  # noqa: F401
     bound_build, bound_floats, bound_level_offset, bound_unpack,
 )
 from ._lib import lib, SoftShadowError, RAY_TILES, SS_MODE_DP, SS_MODE_UNIFORM  # noqa: F401
-from ._lib import SS_MODE_EXACT  # noqa: F401
-from ._lib import SS_SCHED_EQUAL, SS_SCHED_GEOMETRIC  # noqa: F401
+from ._lib import SS_MODE_EXACT, SS_MODE_POINT  # noqa: F401
+from ._lib import SS_SCHED_EQUAL, SS_SCHED_GEOMETRIC, SS_SCHED_LIST  # noqa: F401

@@ -16,8 +16,10 @@ SS_ERR_UNSUPPORTED = -4
 SS_MODE_DP = 0
 SS_MODE_UNIFORM = 1
 SS_MODE_EXACT = 2
+SS_MODE_POINT = 3
 SS_SCHED_GEOMETRIC = 0
 SS_SCHED_EQUAL = 1
+SS_SCHED_LIST = 2
 RAY_TILES = {"8x8": 1, "16x4": 2, "4x16": 3, "32x2": 4}
 
 
@@ -28,7 +30,8 @@ class SSSun(C.Structure):
 class SSParams(C.Structure):
     _fields_ = [("body_radius_m", C.c_double), ("max_len_m", C.c_double), ("n_prime0", C.c_int32),
                 ("schedule", C.c_int32), ("n_segments", C.c_int32), ("mode", C.c_int32),
-                ("uniform_step", C.c_double), ("prune", C.c_int32), ("ray_tile", C.c_int32)]
+                ("uniform_step", C.c_double), ("prune", C.c_int32), ("ray_tile", C.c_int32),
+                ("n_prime_list", C.c_int32 * 16)]
 
 
 class SSTile(C.Structure):

@@ -40,11 +40,13 @@ class Params:
     uniform_step: float = 1.0
     prune: int = 1
     ray_tile: int = 0
+    n_prime_list: tuple = ()
 
     def c(self) -> L.SSParams:
+        lst = (C.c_int32 * 16)(*[int(v) for v in self.n_prime_list][:16])
         return L.SSParams(float(self.radius_m), float(self.max_len_m), int(self.n_prime0),
                           int(self.schedule), int(self.n_segments), int(self.mode),
-                          float(self.uniform_step), int(self.prune), int(self.ray_tile))
+                          float(self.uniform_step), int(self.prune), int(self.ray_tile), lst)
 
 
 def maxmip_levels(width: int, rows: int) -> int:

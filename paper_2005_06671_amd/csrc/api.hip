@@ -142,6 +142,7 @@ extern "C" int32_t ss_bound_build(const float* d_height, int32_t width, int32_t 
 
 struct Resolved {
   int n_prime0, schedule, n_segments, mode, prune, ray_tile;
+  int n_prime_list[16];
   double uniform_step;
   bool sphere;
 };
@@ -151,10 +152,16 @@ static int32_t resolve_params(const ss_params* p, Resolved* r) {
   if (!(p->body_radius_m > 0.0) || isnan(p->body_radius_m)) return SS_ERR_INVALID_ARG;
   if (isnan(p->max_len_m) || isinf(p->max_len_m)) return SS_ERR_INVALID_ARG;
   if (p->n_prime0 < 0 || p->n_prime0 > 64) return SS_ERR_INVALID_ARG;
-  if (p->schedule != SS_SCHED_GEOMETRIC && p->schedule != SS_SCHED_EQUAL) return SS_ERR_INVALID_ARG;
-  if (p->n_segments < 0) return SS_ERR_INVALID_ARG;
-  if (p->mode != SS_MODE_DP && p->mode != SS_MODE_UNIFORM && p->mode != SS_MODE_EXACT)
+  if (p->schedule != SS_SCHED_GEOMETRIC && p->schedule != SS_SCHED_EQUAL &&
+      p->schedule != SS_SCHED_LIST)
     return SS_ERR_INVALID_ARG;
+  if (p->schedule == SS_SCHED_LIST) {
+    if (p->n_segments < 1 || p->n_segments > 16) return SS_ERR_INVALID_ARG;
+    for (int k = 0; k < p->n_segments; ++k)
+      if (p->n_prime_list[k] < 1 || p->n_prime_list[k] > 64) return SS_ERR_INVALID_ARG;
+  }
+  if (p->n_segments < 0) return SS_ERR_INVALID_ARG;
+  if (p->mode < SS_MODE_DP || p->mode > SS_MODE_POINT) return SS_ERR_INVALID_ARG;
   // 0 = default; otherwise at least 1/64 texel so the step count stays bounded
   if (!(p->uniform_step == 0.0 || p->uniform_step >= 1.0 / 64.0) || isinf(p->uniform_step))
     return SS_ERR_INVALID_ARG;
@@ -167,6 +174,7 @@ static int32_t resolve_params(const ss_params* p, Resolved* r) {
   r->prune = p->prune;
   r->ray_tile = p->ray_tile ? p->ray_tile : SS_TILE_8x8;
   r->uniform_step = p->uniform_step > 0.0 ? p->uniform_step : 1.0;
+  for (int k = 0; k < 16; ++k) r->n_prime_list[k] = p->n_prime_list[k];
   r->sphere = !isinf(p->body_radius_m);
   return SS_OK;
 }
@@ -237,9 +245,11 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
   for (;;) {
     if (j >= SS_MAXSEG) return SS_ERR_UNSUPPORTED;
     int np = rp.schedule == SS_SCHED_EQUAL ? rp.n_prime0 : rp.n_prime0 + j;
+    if (rp.schedule == SS_SCHED_LIST) np = rp.n_prime_list[j];
     if (np > L) np = L;
     if (np < 1) np = 1;
     K->m0[j] = np - 1;
+    K->a0[j] = j == 0 ? 0 : K->a0[j - 1] + (2 << K->m0[j - 1]);
     tau += ldexp(delta, np - 1);
     covered += ldexp(1.0, np - 1);
     K->tau[j + 1] = (float)tau;

@@ -54,13 +54,8 @@ __global__ __launch_bounds__(256) void batched_kernel(const TileK* __restrict__ 
         const float hp = T.h[j * T.W + i];
         Ray<SPHERE> r;
         ray_init(T, i, j, hp, r);
-        const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
         unsigned n_lb = 0, n_smp = 0;
-        float alpha;
-        if (MODE == SS_MODE_DP)
-          alpha = shadow_dp(T, r, top, n_lb, n_smp).alpha;
-        else
-          alpha = shadow_uniform(T, r, top, n_smp).alpha;
+        const float alpha = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp).alpha;
         out[j * T.W + i] = disc_fraction(alpha, T);
       }
     }
@@ -98,17 +93,45 @@ static hipError_t launch_bm(const TileK* a, float* const* b, const long long* c,
   }
 }
 
+template <bool SPHERE>
+static hipError_t launch_bs(const TileK* a, float* const* b, const long long* c, const int* d,
+                            unsigned int* e, const BatchDesc& bd, int mode, int ray_tile, int n_wg,
+                            hipStream_t s) {
+  switch (mode) {
+    case SS_MODE_UNIFORM: return launch_bm<SPHERE, SS_MODE_UNIFORM>(a, b, c, d, e, bd, ray_tile, n_wg, s);
+    case SS_MODE_POINT: return launch_bm<SPHERE, SS_MODE_POINT>(a, b, c, d, e, bd, ray_tile, n_wg, s);
+    default: return launch_bm<SPHERE, SS_MODE_DP>(a, b, c, d, e, bd, ray_tile, n_wg, s);
+  }
+}
+
 hipError_t launch_batched(const TileK* d_pairs, float* const* d_out_ptrs, const long long* d_item_start,
                           const int* d_pair_nbx, unsigned int* d_counter, const BatchDesc& bd,
                           bool sphere, int mode, int ray_tile, int n_workgroups, hipStream_t stream) {
   if (bd.item_limit <= 0 || n_workgroups <= 0) return hipSuccess;
   if (sphere)
-    return mode == SS_MODE_DP
-               ? launch_bm<true, SS_MODE_DP>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream)
-               : launch_bm<true, SS_MODE_UNIFORM>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream);
-  return mode == SS_MODE_DP
-             ? launch_bm<false, SS_MODE_DP>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream)
-             : launch_bm<false, SS_MODE_UNIFORM>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, ray_tile, n_workgroups, stream);
+    return launch_bs<true>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, mode,
+                           ray_tile, n_workgroups, stream);
+  return launch_bs<false>(d_pairs, d_out_ptrs, d_item_start, d_pair_nbx, d_counter, bd, mode,
+                          ray_tile, n_workgroups, stream);
+}
+
+template <bool SPHERE, int MODE>
+static const void* kernel_of(int tw) {
+  switch (tw) {
+    case 16: return reinterpret_cast<const void*>(&batched_kernel<SPHERE, 16, MODE>);
+    case 4: return reinterpret_cast<const void*>(&batched_kernel<SPHERE, 4, MODE>);
+    case 32: return reinterpret_cast<const void*>(&batched_kernel<SPHERE, 32, MODE>);
+    default: return reinterpret_cast<const void*>(&batched_kernel<SPHERE, 8, MODE>);
+  }
+}
+
+template <bool SPHERE>
+static const void* kernel_of_mode(int mode, int tw) {
+  switch (mode) {
+    case SS_MODE_UNIFORM: return kernel_of<SPHERE, SS_MODE_UNIFORM>(tw);
+    case SS_MODE_POINT: return kernel_of<SPHERE, SS_MODE_POINT>(tw);
+    default: return kernel_of<SPHERE, SS_MODE_DP>(tw);
+  }
 }
 
 // Workgroups that fit on the device at once for the chosen variant.
@@ -116,21 +139,8 @@ int batched_workgroups(bool sphere, int mode, int ray_tile) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* fn = nullptr;
-#define SS_PICK(S, T, M) reinterpret_cast<const void*>(&batched_kernel<S, T, M>)
   const int tw = ray_tile == SS_TILE_16x4 ? 16 : ray_tile == SS_TILE_4x16 ? 4 : ray_tile == SS_TILE_32x2 ? 32 : 8;
-  if (sphere) {
-    if (mode == SS_MODE_DP)
-      fn = tw == 16 ? SS_PICK(true, 16, 0) : tw == 4 ? SS_PICK(true, 4, 0) : tw == 32 ? SS_PICK(true, 32, 0) : SS_PICK(true, 8, 0);
-    else
-      fn = tw == 16 ? SS_PICK(true, 16, 1) : tw == 4 ? SS_PICK(true, 4, 1) : tw == 32 ? SS_PICK(true, 32, 1) : SS_PICK(true, 8, 1);
-  } else {
-    if (mode == SS_MODE_DP)
-      fn = tw == 16 ? SS_PICK(false, 16, 0) : tw == 4 ? SS_PICK(false, 4, 0) : tw == 32 ? SS_PICK(false, 32, 0) : SS_PICK(false, 8, 0);
-    else
-      fn = tw == 16 ? SS_PICK(false, 16, 1) : tw == 4 ? SS_PICK(false, 4, 1) : tw == 32 ? SS_PICK(false, 32, 1) : SS_PICK(false, 8, 1);
-  }
-#undef SS_PICK
+  const void* fn = sphere ? kernel_of_mode<true>(mode, tw) : kernel_of_mode<false>(mode, tw);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess || per < 1) per = 1;
   return ncu * per;
 }

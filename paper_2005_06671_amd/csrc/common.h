@@ -32,6 +32,7 @@ struct TileK {
   int nseg;                  // number of concatenated runs
   int m0[SS_MAXSEG];         // top mip level of run j
   float tau[SS_MAXSEG + 1];  // ray length where run j starts (tau[nseg] = end)
+  int a0[SS_MAXSEG];         // grid index of run j's start: tau_j = (a0_j + 1) delta/2
   int prune;                 // 1: result-invariant early exits enabled
   int pad_;
 };

@@ -398,6 +398,72 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   out.valid = 1;
 }
 
+// One run of Alg. 1 read literally: point samples instead of the texels the
+// ray crosses.  Positions along run j are indices n on the half-texel grid
+// t_n = (n + 1) delta/2 (the algorithm's normalised t in [0, 1] is
+// (n - a_j) / 2^(m0+1)).  Level m = m0 .. 1 reads the maximum mipmap at the
+// level-m texel under the ray tip at n = a_j + K, a_j + K - 2^m and
+// a_j + K - 2^(m+1) (far to near; strict '<' keeps the far one on a tie) and
+// continues from the smallest H - max h at K* with K = K* + 2^m; K starts at
+// 2^(m0+1).  Level 0 samples the heightfield bilinearly at the three grid
+// points and the chosen sample's clearance is the run's.  A level with no
+// sample inside the tile ends the run.
+template <bool SPHERE>
+__device__ __forceinline__ void point_run(const TileK& T, const Ray<SPHERE>& r, int jseg,
+                                          SegOut& out, unsigned& n_lb, unsigned& n_smp) {
+  out.valid = 0;
+  const int m0 = T.m0[jseg];
+  const int a = T.a0[jseg];
+  int K = 2 << m0;
+  for (int m = m0; m >= 1; --m) {
+    const int step = 1 << m;
+    const Level Lm = level_of(T, m);
+    float best = SS_INF;
+    int kstar = -1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int kk = K - q * step;
+      const float t = (float)(a + kk + 1) * T.half_delta;
+      const float u = t_to_u(r, t);
+      // texel under the tip (positions before the edge are >= 0 by construction)
+      const int cx = (int)floorf((float)r.i + 0.5f + r.Kx * u) >> m;
+      const int cy = (int)floorf((float)r.j + 0.5f + r.Ky * u) >> m;
+      const bool ok = u < r.uexit && (unsigned)cx < (unsigned)T.lw[m] && (unsigned)cy < (unsigned)T.lh[m];
+      const float v = tip_rise(r, T, t) - (level_at(Lm, cx, cy) - r.hp);
+      n_lb += ok ? 1u : 0u;
+      const bool take = ok && v < best;
+      best = take ? v : best;
+      kstar = take ? kk : kstar;
+    }
+    if (kstar < 0) return;
+    K = kstar + step;
+  }
+  float bdh = SS_INF, bt = 0.0f, bu = 0.0f;
+  int found = 0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const float t = (float)(a + K - q + 1) * T.half_delta;
+    const float u = t_to_u(r, t);
+    if (u < r.uexit) {
+      const Sample s = sample_at(r, T, t, u);
+      n_smp++;
+      if (s.dh < bdh) {
+        bdh = s.dh;
+        bt = t;
+        bu = u;
+        found = 1;
+      }
+    }
+  }
+  if (!found) return;
+  float num, den;
+  clearance_terms(r, bt, bdh, num, den);
+  out.key = tangent_key(num, den);
+  out.t = bt;
+  out.u = bu;
+  out.valid = 1;
+}
+
 // True when every sample at ray length >= t clears the angle whose tangent is
 // need_tan (an angle in (-pi/2, pi/2)), given that no terrain rises above
 // `top` (relative to h_p, >= 0): the clearance of the point at that height
@@ -430,8 +496,9 @@ __device__ __forceinline__ float angle_of(float key) {
   return key == SS_INF ? SS_INF : (key == -SS_INF ? -SS_INF : atanf(key));
 }
 
-// Smallest clearance over the concatenated runs (Sec. 3.3).
-template <bool SPHERE>
+// Smallest clearance over the concatenated runs (Sec. 3.3), each by the
+// texel descent (POINT = false) or Alg. 1's point samples (POINT = true).
+template <bool SPHERE, bool POINT = false>
 __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>& r, float top,
                                                unsigned& n_lb, unsigned& n_smp) {
   RayResult res;
@@ -449,7 +516,10 @@ __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>
       if (clears(r, T, tlo, top, need)) break;  // nothing ahead is high enough
     }
     SegOut so;
-    descend_run(T, r, j, so, n_lb, n_smp);
+    if (POINT)
+      point_run(T, r, j, so, n_lb, n_smp);
+    else
+      descend_run(T, r, j, so, n_lb, n_smp);
     if (so.valid && so.key < best) {
       best = so.key;
       res.t = so.t;
@@ -607,4 +677,16 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
   res.key = best;
   res.alpha = angle_of(best);
   return res;
+}
+
+// The shadow clearance of one ray by the chosen method.
+template <bool SPHERE, int MODE>
+__device__ __forceinline__ RayResult trace_ray(const TileK& T, const Ray<SPHERE>& r, unsigned& n_lb,
+                                               unsigned& n_smp) {
+  // no terrain rises above `top` (relative to h_p, at least 0)
+  const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp : 0.0f;
+  if (MODE == SS_MODE_EXACT) return shadow_exact(T, r, top, n_lb, n_smp);
+  if (MODE == SS_MODE_POINT) return shadow_dp<SPHERE, true>(T, r, top, n_lb, n_smp);
+  if (MODE == SS_MODE_UNIFORM) return shadow_uniform(T, r, top, n_smp);
+  return shadow_dp<SPHERE, false>(T, r, top, n_lb, n_smp);
 }

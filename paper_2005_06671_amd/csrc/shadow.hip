@@ -48,14 +48,7 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
-    const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
-    float alpha;
-    if (MODE == SS_MODE_EXACT)
-      alpha = shadow_exact(T, r, top, n_lb, n_smp).alpha;
-    else if (MODE == SS_MODE_DP)
-      alpha = shadow_dp(T, r, top, n_lb, n_smp).alpha;
-    else
-      alpha = shadow_uniform(T, r, top, n_smp).alpha;
+    const float alpha = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp).alpha;
     out[j * T.W + i] = disc_fraction(alpha, T);
   }
   if (COUNT) {
@@ -65,15 +58,6 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
       if (b) atomicAdd(&counter[1], (unsigned long long)b);
     }
   }
-}
-
-template <bool SPHERE, int MODE>
-__device__ __forceinline__ RayResult forward_of(const TileK& T, const Ray<SPHERE>& r, float hp) {
-  unsigned n_lb = 0, n_smp = 0;
-  const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), hp) - hp : 0.0f;
-  if (MODE == SS_MODE_EXACT) return shadow_exact(T, r, top, n_lb, n_smp);
-  if (MODE == SS_MODE_DP) return shadow_dp(T, r, top, n_lb, n_smp);
-  return shadow_uniform(T, r, top, n_smp);
 }
 
 // Adjoint: recompute the forward decisions, then apply the chain rule through
@@ -100,7 +84,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
-    const RayResult res = forward_of<SPHERE, MODE>(T, r, hp);
+    unsigned n_lb = 0, n_smp = 0;
+    const RayResult res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp);
     const float dd = res.alpha * T.inv_rL;
     if (res.valid && g != 0.0f && fabsf(dd) < 1.0f) {
       const float t = res.t, u = res.u;
@@ -256,6 +241,13 @@ static hipError_t launch_fwd_tw(const TileK& T, int mode, bool count, float* out
     else
       hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_EXACT, false>), grid, block, 0,
                          stream, T, out, counter, nbx, nb);
+  } else if (mode == SS_MODE_POINT) {
+    if (count)
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_POINT, true>), grid, block, 0, stream,
+                         T, out, counter, nbx, nb);
+    else
+      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_POINT, false>), grid, block, 0,
+                         stream, T, out, counter, nbx, nb);
   } else {
     if (count)
       hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_UNIFORM, true>), grid, block, 0, stream,
@@ -296,6 +288,8 @@ static void adjoint_mode(const TileK& T, int mode, const SunTrig& st, const floa
                          double* gsun, int nbx, int nb, hipStream_t stream) {
   if (mode == SS_MODE_EXACT)
     adjoint_launch<SPHERE, SS_MODE_EXACT>(T, st, gs, gh, gsun, nbx, nb, stream);
+  else if (mode == SS_MODE_POINT)
+    adjoint_launch<SPHERE, SS_MODE_POINT>(T, st, gs, gh, gsun, nbx, nb, stream);
   else if (mode == SS_MODE_UNIFORM)
     adjoint_launch<SPHERE, SS_MODE_UNIFORM>(T, st, gs, gh, gsun, nbx, nb, stream);
   else

@@ -96,6 +96,14 @@ def test_rejects_bad_arguments(L):
     p2.n_prime0 = 1
     p2.max_len_m = 1e6
     assert cast(L, t, s, p2) == L.SS_ERR_UNSUPPORTED
+    # an explicit run schedule needs 1..16 runs of >= 1 level
+    for nseg, lst in [(0, (5,)), (17, (5,) * 16), (2, (5, 0))]:
+        _, _, p4 = good(L)
+        p4.schedule = 2
+        p4.n_segments = nseg
+        for k, v in enumerate(lst):
+            p4.n_prime_list[k] = v
+        assert cast(L, t, s, p4) == L.SS_ERR_INVALID_ARG, (nseg, lst)
     # the exact mode needs the tap-bound pyramid, forward and backward
     _, _, p3 = good(L)
     p3.mode = L.SS_MODE_EXACT

@@ -66,11 +66,12 @@ CASES = [((256, 256), 20.0, R, 1.5, 0.7, 0.0), ((192, 256), 20.0, math.inf, 2.0,
          ((256, 240), 15.0, R, 1.0, 4.1, 1500.0)]
 
 
-@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("mode", [0, 2, 3])
 @pytest.mark.parametrize("shape,D,radius,e_deg,az,cap", CASES)
 def test_adjoint_matches_reference_gradient(ss, shape, D, radius, e_deg, az, cap, mode):
-    """Descent (mode 0) and exact mode (2): in both the deciding sample sits at
-    t = (n + 1) delta/2, the chain the reference differentiates."""
+    """Descent (mode 0), exact mode (2) and point descent (3): in each the
+    deciding sample sits at t = (n + 1) delta/2, the chain the reference
+    differentiates."""
     h = rough(shape, shape[0] + 3, 80.0)
     p = oracle.Params(shape[1], shape[0], D, radius, math.radians(e_deg), az, RL, max_len_m=cap,
                       mode=mode)
