@@ -226,12 +226,14 @@ def leg_accuracy(ss, h, mm, D, suns, c):
     pu2 = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM,
                     uniform_step=0.5)
     px = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_EXACT)
+    pp = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_POINT)
     bound = ss.bound_build(h)
     t_bound = _timed(lambda: ss.bound_build(h, out=bound), 3)
-    dp, u1, u2, ex = [], [], [], []
+    dp, u1, u2, ex, pt = [], [], [], [], []
     t_u2, t_ex, cnt = [], [], []
     for (e, a, r) in suns:
         dp.append(ss.shadow_cast(h, D, e, a, r, pd, mm=mm))
+        pt.append(ss.shadow_cast(h, D, e, a, r, pp, mm=mm))
         u1.append(ss.shadow_cast(h, D, e, a, r, pu1, mm=mm))
         o2 = torch.empty_like(h)
         ox = torch.empty_like(h)
@@ -243,6 +245,7 @@ def leg_accuracy(ss, h, mm, D, suns, c):
         _, k = ss.shadow_cast_counted(h, D, e, a, r, px, mm=mm, bound=bound)
         cnt.append([int(v) for v in k.cpu().tolist()])
     dp, u1, u2, ex = torch.stack(dp), torch.stack(u1), torch.stack(u2), torch.stack(ex)
+    pt = torch.stack(pt)
     rays = W * H * len(suns)
     exact = {"mrays_s": rays / (sum(t_ex) / 1e3) / 1e6,
              "dense_mrays_s": rays / (sum(t_u2) / 1e3) / 1e6,
@@ -253,8 +256,42 @@ def leg_accuracy(ss, h, mm, D, suns, c):
              "samples_per_ray": sum(k[1] for k in cnt) / rays,
              "launch_ms": t_ex}
     return {"reference": "uniform stepping at delta/2 (dense half-texel grid), all suns",
-            "descent": _err_stats(dp, u2), "uniform_1_texel": _err_stats(u1, u2),
+            "descent": _err_stats(dp, u2), "point_descent": _err_stats(pt, u2),
+            "uniform_1_texel": _err_stats(u1, u2),
             "mean_s_dense": float(u2.mean())}, exact
+
+
+def leg_schedules(ss, h, mm, D, suns):
+    """The paper's step-count study (Sec. 6.3) on the tile DEM: runs {5,5,5}
+    against {5,5,5,3} for the point-sample descent (Alg. 1 as printed) and the
+    texel descent, and uniform stepping with 100 one-texel steps; per-launch
+    time averaged over the suns, and grid samples evaluated per ray."""
+    from synth import R_MOON
+    W, H = h.shape[1], h.shape[0]
+    cfg = {"555": dict(schedule=ss.SS_SCHED_EQUAL, n_segments=3),
+           "5553": dict(schedule=ss.SS_SCHED_LIST, n_segments=4, n_prime_list=(5, 5, 5, 3))}
+    res = {}
+    for mode_name, mode in (("point", ss.SS_MODE_POINT), ("descent", ss.SS_MODE_DP)):
+        for k, kw in cfg.items():
+            p = ss.Params(radius_m=R_MOON, mode=mode, **kw)
+            ts, ev = [], []
+            for (e, a, r) in suns:
+                ss.shadow_cast(h, D, e, a, r, p, mm=mm)
+                ts += _timed(lambda: ss.shadow_cast(h, D, e, a, r, p, mm=mm), 1)
+                _, c = ss.shadow_cast_counted(h, D, e, a, r, p, mm=mm)
+                ev.append(sum(int(v) for v in c.cpu().tolist()))
+            res[f"{mode_name}_{k}"] = {"launch_ms": sum(ts) / len(ts),
+                                       "evals_per_ray": sum(ev) / len(ev) / (W * H)}
+    pu = ss.Params(radius_m=R_MOON, mode=ss.SS_MODE_UNIFORM, max_len_m=100.0 * D)
+    ts = []
+    for (e, a, r) in suns:
+        ss.shadow_cast(h, D, e, a, r, pu, mm=mm)
+        ts += _timed(lambda: ss.shadow_cast(h, D, e, a, r, pu, mm=mm), 1)
+    res["uniform_100_steps"] = {"launch_ms": sum(ts) / len(ts)}
+    for m in ("point", "descent"):
+        res[f"{m}_time_ratio_5553_over_555"] = res[f"{m}_5553"]["launch_ms"] / res[f"{m}_555"]["launch_ms"]
+    res["uniform_100_over_point_555"] = res["uniform_100_steps"]["launch_ms"] / res["point_555"]["launch_ms"]
+    return res
 
 
 def leg_cold_maxmip(ss, h, mm, mm_bytes, reps=5):
@@ -479,6 +516,7 @@ def main():
     if not args.no_extras:
         extras["accuracy_vs_dense"], extras["exact_mode"] = leg_accuracy(ss, h, mm, D, suns, c)
         maxmip["cold"] = leg_cold_maxmip(ss, h, mm, mm_bytes)
+        extras["schedule_study"] = leg_schedules(ss, h, mm, D, suns)
         # uniform stepping, one texel per step, same suns, cap and exits
         pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
         for k, (e, a, r) in enumerate(suns[:1]):
