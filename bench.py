@@ -127,7 +127,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, counters_dir, out_dir):
     with open(os.path.join(out_dir, "bench_tile_kernel_stats.txt"), "w") as f:
         f.write("# rocprofv3 --kernel-trace --stats summary of the tile benchmark\n")
         f.write("# command: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
-                "python bench.py --steps 5 --warmup 1 --no-cpu --dem-cache /tmp/dem_tile.npy\n")
+                "python bench.py --steps 5 --warmup 1 --no-cpu --no-extras --dem-cache /tmp/dem_tile.npy\n")
         f.write("\n".join(lines) + "\n")
 
     def per_kernel(d, counter):
