@@ -323,20 +323,31 @@ def leg_diff(ss, reps=5):
     gh = torch.zeros_like(h)
     gs = torch.zeros(2, dtype=torch.float64, device=h.device)
 
+    sample = torch.empty(h.shape, dtype=torch.int32, device=h.device)
+
     def fwd():
         ss.maxmip(h, out=mm)
         ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out)
 
     def fwd_bwd():
+        # recorded forward, adjoint from the record
+        ss.maxmip(h, out=mm)
+        ss.shadow_cast_save(h, D, e, a, r, p, mm=mm, out=out, sample=sample)
+        ss.shadow_cast_backward_saved(h, D, e, a, sample, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+
+    def fwd_bwd_replay():
         fwd()
         ss.shadow_cast_backward(h, D, e, a, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
 
     fwd_bwd()
+    fwd_bwd_replay()
     tf = _timed(fwd, reps)
     tb = _timed(fwd_bwd, reps)
+    tr = _timed(fwd_bwd_replay, reps)
     n = W * H
     return {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
-            "fwd_ms": min(tf), "fwd_bwd_ms": min(tb)}
+            "fwd_bwd_replay_mrays_s": n / (min(tr) / 1e3) / 1e6,
+            "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "fwd_bwd_replay_ms": min(tr)}
 
 
 def leg_batched(ss, reps=3):
@@ -379,10 +390,14 @@ def leg_polar(ss, reps=3):
     gh = torch.zeros_like(h)
     gs = torch.zeros(2, dtype=torch.float64, device=h.device)
 
-    def fwd_bwd():
-        fwd()
-        ss.shadow_cast_backward(h, D, e, a, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+    sample = torch.empty(h.shape, dtype=torch.int32, device=h.device)
 
+    def fwd_bwd():
+        ss.maxmip(h, out=mm)
+        ss.shadow_cast_save(h, D, e, a, r, p, mm=mm, out=out, sample=sample)
+        ss.shadow_cast_backward_saved(h, D, e, a, sample, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+
+    fwd_bwd()
     tb = _timed(fwd_bwd, 1)
     n = W * H
     mean_s = float(out.mean())
@@ -536,20 +551,30 @@ def main():
             _, cnt = ss.shadow_cast_counted(h, D, e, a, r, pu, mm=mm)
             ucnt.append(int(cnt[1].item()))
         extras["uniform_steps_per_ray"] = float(np.mean(ucnt)) / (W * H)
-        # forward + backward (hand-written adjoint) for every sun
+        # forward + backward (hand-written adjoint) for every sun: the recorded
+        # forward with the adjoint reading the record, and the replaying adjoint
         g = torch.randn(H, W, generator=torch.Generator(device="cpu").manual_seed(7)).to(dev)
         gh = torch.zeros_like(h)
         gsun = torch.zeros(2, dtype=torch.float64, device=dev)
-        for rep in range(2):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ss.maxmip(h, out=mm)
-            for k, (e, a, r) in enumerate(suns):
-                ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
-                ss.shadow_cast_backward(h, D, e, a, g, r, params, mm=mm, grad_h=gh, grad_sun=gsun)
-            torch.cuda.synchronize()
-            tfb = time.perf_counter() - t0
-        extras["fwd_bwd_mrays_s"] = rays_per_step / tfb / 1e6
+        samples = [torch.empty(h.shape, dtype=torch.int32, device=dev) for _ in suns]
+        for replay in (False, True):
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ss.maxmip(h, out=mm)
+                for k, (e, a, r) in enumerate(suns):
+                    if replay:
+                        ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
+                        ss.shadow_cast_backward(h, D, e, a, g, r, params, mm=mm, grad_h=gh,
+                                                grad_sun=gsun)
+                    else:
+                        ss.shadow_cast_save(h, D, e, a, r, params, mm=mm, out=outs[k],
+                                            sample=samples[k])
+                        ss.shadow_cast_backward_saved(h, D, e, a, samples[k], g, r, params, mm=mm,
+                                                      grad_h=gh, grad_sun=gsun)
+                torch.cuda.synchronize()
+                tfb = time.perf_counter() - t0
+            extras["fwd_bwd_replay_mrays_s" if replay else "fwd_bwd_mrays_s"] = rays_per_step / tfb / 1e6
         extras["differentiable_2048"] = leg_diff(ss)
         if not args.no_big:
             extras["batched_8x64"] = leg_batched(ss)

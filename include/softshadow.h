@@ -159,6 +159,24 @@ int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun, const ss
                                 const float* d_grad_shadow, float* d_grad_height,
                                 double* d_grad_sun, void* stream);
 
+/* Forward that also records, for every ray, the index n of its deciding
+ * sample (the one whose clearance gave s): t = delta/2 + n * step with
+ * step = delta/2, or the uniform step in SS_MODE_UNIFORM; -1 when no sample
+ * decided (s = 1 with no terrain in view).  d_sample is int32 [rows][width],
+ * overwritten.  d_shadow is bit-identical to ss_shadow_cast's.  The record is
+ * what ss_shadow_cast_backward_saved needs, 4 bytes per ray. */
+int32_t ss_shadow_cast_save(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                            float* d_shadow, int32_t* d_sample, void* stream);
+
+/* ss_shadow_cast_backward from a record of ss_shadow_cast_save with the same
+ * tile, sun and params: the same accumulation (+=) without replaying the
+ * forward's decisions.  Up to the order of the atomic sums it equals
+ * ss_shadow_cast_backward. */
+int32_t ss_shadow_cast_backward_saved(const ss_tile* tile, const ss_sun* sun,
+                                      const ss_params* params, const int32_t* d_sample,
+                                      const float* d_grad_shadow, float* d_grad_height,
+                                      double* d_grad_sun, void* stream);
+
 /* ---- batched: many suns over tiles of uneven size ------------------------ */
 
 /* Bytes of device workspace ss_shadow_cast_batched needs (-1: bad sizes). */

@@ -58,6 +58,11 @@ SIGNATURES = {
     "ss_shadow_cast_backward": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun),
                                             C.POINTER(SSParams), C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p]),
+    "ss_shadow_cast_save": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
+                                        C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ss_shadow_cast_backward_saved": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun),
+                                                  C.POINTER(SSParams), C.c_void_p, C.c_void_p,
+                                                  C.c_void_p, C.c_void_p, C.c_void_p]),
     "ss_batched_workspace_bytes": (C.c_int64, [C.c_int32, C.c_int32]),
     "ss_shadow_cast_batched": (C.c_int32, [C.POINTER(SSTile), C.c_int32, C.POINTER(SSSun),
                                            C.c_int32, C.POINTER(SSParams), C.c_void_p, C.c_void_p,

@@ -199,9 +199,60 @@ def shadow_cast_backward(h, texel_m, elev, azim, grad_s, ang_radius=SUN_RADIUS_R
     return grad_h, grad_sun
 
 
+def shadow_cast_save(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=None, mm=None,
+                     out=None, bound=None, sample=None):
+    """(s, sample): s as shadow_cast, and each ray's deciding sample index (int32, -1 none)."""
+    _dev_f32_2d(h)
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
+    if out is None:
+        out = torch.empty_like(h)
+    if sample is None:
+        sample = torch.empty(h.shape, dtype=torch.int32, device=h.device)
+    elif sample.shape != h.shape or sample.dtype != torch.int32 or not sample.is_contiguous():
+        raise ValueError("sample must be a contiguous int32 tensor shaped like h")
+    t = _tile(h, mm, texel_m, bound)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_cast_save",
+            L.lib().ss_shadow_cast_save(C.byref(t), C.byref(s), C.byref(p), out.data_ptr(),
+                                        sample.data_ptr(), _stream(h.device)))
+    return out, sample
+
+
+def shadow_cast_backward_saved(h, texel_m, elev, azim, sample, grad_s, ang_radius=SUN_RADIUS_RAD,
+                               params=None, mm=None, grad_h=None, grad_sun=None, bound=None):
+    """shadow_cast_backward from the record of shadow_cast_save (no replay)."""
+    _dev_f32_2d(h)
+    _dev_f32_2d(grad_s, "grad_s")
+    if sample.shape != h.shape or sample.dtype != torch.int32 or not sample.is_contiguous():
+        raise ValueError("sample must be a contiguous int32 tensor shaped like h")
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
+    if grad_h is None:
+        grad_h = torch.zeros_like(h)
+    if grad_sun is None:
+        grad_sun = torch.zeros(2, dtype=torch.float64, device=h.device)
+    t = _tile(h, mm, texel_m, bound)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_cast_backward_saved",
+            L.lib().ss_shadow_cast_backward_saved(C.byref(t), C.byref(s), C.byref(p),
+                                                  sample.data_ptr(), grad_s.data_ptr(),
+                                                  grad_h.data_ptr(), grad_sun.data_ptr(),
+                                                  _stream(h.device)))
+    return grad_h, grad_sun
+
+
 class ShadowCast(torch.autograd.Function):
     """s = shadow(h, elev, azim) with the hand-written adjoint kernel as backward.
 
+    The forward records each ray's deciding sample (4 bytes per ray), so the
+    backward applies the chain rule without replaying the descent.
     h: float32 CUDA [rows, width]; elev, azim: 0-d float64 tensors (CPU or CUDA).
     Gradients: dL/dh float32 (same device as h), dL/delev and dL/dazim float64.
     """
@@ -213,18 +264,18 @@ class ShadowCast(torch.autograd.Function):
         hd = h.detach().contiguous()
         mm = maxmip(hd)
         bound = _bound_for(hd, params, None)
-        s = shadow_cast(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound)
-        ctx.save_for_backward(hd, mm, bound)
+        s, sample = shadow_cast_save(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound)
+        ctx.save_for_backward(hd, mm, bound, sample)
         ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim)
         return s
 
     @staticmethod
     def backward(ctx, grad_s):
-        hd, mm, bound = ctx.saved_tensors
+        hd, mm, bound, sample = ctx.saved_tensors
         texel_m, e, a, ang_radius, params, elev, azim = ctx.cfg
         g = grad_s.contiguous()
-        gh, gsun = shadow_cast_backward(hd, texel_m, e, a, g, ang_radius, params, mm=mm,
-                                        bound=bound)
+        gh, gsun = shadow_cast_backward_saved(hd, texel_m, e, a, sample, g, ang_radius, params,
+                                              mm=mm, bound=bound)
         ge = gsun[0].to(elev.device) if isinstance(elev, torch.Tensor) else None
         ga = gsun[1].to(azim.device) if isinstance(azim, torch.Tensor) else None
         return gh, ge, ga, None, None, None

@@ -275,7 +275,8 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
 // ------------------------------------------------------------------------
 
 static int32_t cast_common(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
-                           float* d_shadow, unsigned long long* counter, void* stream) {
+                           float* d_shadow, unsigned long long* counter, int32_t* d_sample,
+                           void* stream) {
   Resolved rp;
   int32_t rc = resolve_params(params, &rp);
   if (rc) return rc;
@@ -286,25 +287,32 @@ static int32_t cast_common(const ss_tile* tile, const ss_sun* sun, const ss_para
   TileK K;
   if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
   SS_HIP(launch_forward(K, rp.sphere, rp.mode, rp.ray_tile, counter != nullptr, d_shadow, counter,
-                        (hipStream_t)stream));
+                        d_sample, (hipStream_t)stream));
   return SS_OK;
 }
 
 extern "C" int32_t ss_shadow_cast(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                                   float* d_shadow, void* stream) {
-  return cast_common(tile, sun, params, d_shadow, nullptr, stream);
+  return cast_common(tile, sun, params, d_shadow, nullptr, nullptr, stream);
 }
 
 extern "C" int32_t ss_shadow_cast_counted(const ss_tile* tile, const ss_sun* sun,
                                           const ss_params* params, float* d_shadow,
                                           unsigned long long* d_eval_count, void* stream) {
   if (!d_eval_count) return SS_ERR_INVALID_ARG;
-  return cast_common(tile, sun, params, d_shadow, d_eval_count, stream);
+  return cast_common(tile, sun, params, d_shadow, d_eval_count, nullptr, stream);
 }
 
-extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun,
-                                           const ss_params* params, const float* d_grad_shadow,
-                                           float* d_grad_height, double* d_grad_sun, void* stream) {
+extern "C" int32_t ss_shadow_cast_save(const ss_tile* tile, const ss_sun* sun,
+                                       const ss_params* params, float* d_shadow,
+                                       int32_t* d_sample, void* stream) {
+  if (!d_sample && tile && tile->width > 0 && tile->rows > 0) return SS_ERR_INVALID_ARG;
+  return cast_common(tile, sun, params, d_shadow, nullptr, d_sample, stream);
+}
+
+static int32_t backward_common(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                               const int32_t* d_sample, const float* d_grad_shadow,
+                               float* d_grad_height, double* d_grad_sun, void* stream) {
   Resolved rp;
   int32_t rc = resolve_params(params, &rp);
   if (rc) return rc;
@@ -315,8 +323,24 @@ extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* su
   TileK K;
   if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
   SS_HIP(launch_adjoint(K, rp.sphere, rp.mode, sun->elev_rad, sun->azim_rad, d_grad_shadow,
-                        d_grad_height, d_grad_sun, (hipStream_t)stream));
+                        d_sample, d_grad_height, d_grad_sun, (hipStream_t)stream));
   return SS_OK;
+}
+
+extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun,
+                                           const ss_params* params, const float* d_grad_shadow,
+                                           float* d_grad_height, double* d_grad_sun, void* stream) {
+  return backward_common(tile, sun, params, nullptr, d_grad_shadow, d_grad_height, d_grad_sun,
+                         stream);
+}
+
+extern "C" int32_t ss_shadow_cast_backward_saved(const ss_tile* tile, const ss_sun* sun,
+                                                 const ss_params* params, const int32_t* d_sample,
+                                                 const float* d_grad_shadow, float* d_grad_height,
+                                                 double* d_grad_sun, void* stream) {
+  if (!d_sample && tile && tile->width > 0 && tile->rows > 0) return SS_ERR_INVALID_ARG;
+  return backward_common(tile, sun, params, d_sample, d_grad_shadow, d_grad_height, d_grad_sun,
+                         stream);
 }
 
 // ------------------------------------------------------------------------
@@ -552,7 +576,7 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
     if (rc) return rc;
     for (int rep = 0; rep < 2; ++rep) {
       SS_HIP(hipEventRecord(a, s));
-      SS_HIP(launch_forward(K, r2.sphere, r2.mode, sh, false, out, nullptr, s));
+      SS_HIP(launch_forward(K, r2.sphere, r2.mode, sh, false, out, nullptr, nullptr, s));
       SS_HIP(hipEventRecord(b, s));
       const double ms = time_ms(s, a, b);
       if (rep > 0 && ms < best) {

@@ -15,11 +15,15 @@ hipError_t launch_block3_max(const float* src, int W, int H, float* dst, hipStre
 
 void grid_for(const TileK& T, int ray_tile, int* nbx, int* nblocks);
 
+// sample != nullptr (and !count): also record each ray's deciding sample index.
 hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, bool count,
-                          float* out, unsigned long long* counter, hipStream_t stream);
+                          float* out, unsigned long long* counter, int* sample,
+                          hipStream_t stream);
 
+// sample != nullptr: take the deciding samples from there instead of replaying.
 hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
-                          const float* gs, float* gh, double* gsun, hipStream_t stream);
+                          const float* gs, const int* sample, float* gh, double* gsun,
+                          hipStream_t stream);
 
 // Persistent batched launch over (tile, sun, ray block) items.
 struct BatchDesc {

@@ -216,6 +216,7 @@ struct SegOut {
   float key;
   float t;        // ray length of the deciding sample
   float u;
+  int n;          // its index on the half-texel grid
   int valid;
 };
 
@@ -372,7 +373,7 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   const float tmid = 0.5f * (tin + tout);
   const int nc = (int)floorf((tmid - T.half_delta) * T.two_over_delta + 0.5f);
   float bdh = SS_INF, bt = 0.0f, bu = 0.0f;
-  int found = 0;
+  int found = 0, bn = -1;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int n = nc - 1 + k;
@@ -385,6 +386,7 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
         bdh = s.dh;
         bt = t;
         bu = u;
+        bn = n;
         found = 1;
       }
     }
@@ -395,6 +397,7 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   out.key = tangent_key(num, den);
   out.t = bt;
   out.u = bu;
+  out.n = bn;
   out.valid = 1;
 }
 
@@ -439,7 +442,7 @@ __device__ __forceinline__ void point_run(const TileK& T, const Ray<SPHERE>& r, 
     K = kstar + step;
   }
   float bdh = SS_INF, bt = 0.0f, bu = 0.0f;
-  int found = 0;
+  int found = 0, bn = -1;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const float t = (float)(a + K - q + 1) * T.half_delta;
@@ -451,6 +454,7 @@ __device__ __forceinline__ void point_run(const TileK& T, const Ray<SPHERE>& r, 
         bdh = s.dh;
         bt = t;
         bu = u;
+        bn = a + K - q;
         found = 1;
       }
     }
@@ -461,6 +465,7 @@ __device__ __forceinline__ void point_run(const TileK& T, const Ray<SPHERE>& r, 
   out.key = tangent_key(num, den);
   out.t = bt;
   out.u = bu;
+  out.n = bn;
   out.valid = 1;
 }
 
@@ -489,6 +494,7 @@ struct RayResult {
   float alpha;
   float key;      // tangent key of alpha (orders like alpha)
   float t, u;     // deciding sample
+  int n;          // its index on the step grid t = delta/2 + n step
   int valid;
 };
 
@@ -504,6 +510,7 @@ __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>
   RayResult res;
   res.t = 0.0f;
   res.u = 0.0f;
+  res.n = -1;
   res.valid = 0;
   float best = SS_INF;                    // tangent key of the smallest clearance so far
   float need = need_tangent(T, SS_INF);   // tan(min(alpha, r_L) + margin)
@@ -524,6 +531,7 @@ __device__ __forceinline__ RayResult shadow_dp(const TileK& T, const Ray<SPHERE>
       best = so.key;
       res.t = so.t;
       res.u = so.u;
+      res.n = so.n;
       res.valid = 1;
       need = need_tangent(T, best);
     }
@@ -549,6 +557,7 @@ __device__ __forceinline__ RayResult shadow_uniform(const TileK& T, const Ray<SP
   RayResult res;
   res.t = 0.0f;
   res.u = 0.0f;
+  res.n = -1;
   res.valid = 0;
   float best = SS_INF;
   for (int k = 0; k < (1 << 22); ++k) {
@@ -569,6 +578,7 @@ __device__ __forceinline__ RayResult shadow_uniform(const TileK& T, const Ray<SP
       best = key;
       res.t = t;
       res.u = u;
+      res.n = k;
       res.valid = 1;
     }
   }
@@ -612,6 +622,7 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
   RayResult res;
   res.t = 0.0f;
   res.u = 0.0f;
+  res.n = -1;
   res.valid = 0;
   float best = SS_INF;
   if (T.prune) {
@@ -667,6 +678,7 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
         best = key;
         res.t = t;
         res.u = u;
+        res.n = n;
         res.valid = 1;
         need = need_tangent(T, best);
         if (T.prune && best <= -T.tan_rL) break;  // umbra: nothing can change s = 0

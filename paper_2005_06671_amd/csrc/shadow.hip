@@ -27,20 +27,31 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   return v;
 }
 
+// Texel of this lane in ray block b (2 x 2 wavefront tiles of TW x 64/TW).
 template <int TW>
-__device__ __forceinline__ void ray_coords(int nbx, int nblocks, int& i, int& j) {
+__device__ __forceinline__ void coords_of(int b, int nbx, int& i, int& j) {
   constexpr int TH = 64 / TW;
-  const int b = xcd_remap((int)blockIdx.x, nblocks);
   const int bxi = b % nbx, byi = b / nbx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   i = bxi * (2 * TW) + (wave & 1) * TW + lane % TW;
   j = byi * (2 * TH) + (wave >> 1) * TH + lane / TW;
 }
 
-template <bool SPHERE, int TW, int MODE, bool COUNT>
+template <int TW>
+__device__ __forceinline__ void ray_coords(int nbx, int nblocks, int& i, int& j) {
+  coords_of<TW>(xcd_remap((int)blockIdx.x, nblocks), nbx, i, j);
+}
+
+// FLAGS: FWD_COUNT adds the work units to counter[0..1]; FWD_SAVE writes each
+// ray's deciding sample index (-1: none) to sample[].
+enum { FWD_PLAIN = 0, FWD_COUNT = 1, FWD_SAVE = 2 };
+
+template <bool SPHERE, int TW, int MODE, int FLAGS>
 __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict__ out,
-                                                     unsigned long long* counter, int nbx,
+                                                     unsigned long long* counter,
+                                                     int* __restrict__ sample, int nbx,
                                                      int nblocks) {
+  constexpr bool COUNT = FLAGS == FWD_COUNT;
   int i, j;
   ray_coords<TW>(nbx, nblocks, i, j);
   unsigned n_lb = 0, n_smp = 0;
@@ -48,8 +59,9 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
-    const float alpha = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp).alpha;
-    out[j * T.W + i] = disc_fraction(alpha, T);
+    const RayResult res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp);
+    out[j * T.W + i] = disc_fraction(res.alpha, T);
+    if (FLAGS == FWD_SAVE) sample[j * T.W + i] = res.valid ? res.n : -1;
   }
   if (COUNT) {
     const unsigned a = wave_sum_u32(n_lb), b = wave_sum_u32(n_smp);
@@ -60,8 +72,8 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
   }
 }
 
-// Adjoint: recompute the forward decisions, then apply the chain rule through
-// the deciding sample.  With the decisions fixed, s depends on the origin
+// Adjoint: recompute the forward decisions (or read the deciding sample the
+// forward recorded, SAVED), then apply the chain rule through that sample.  With the decisions fixed, s depends on the origin
 // height (through rho and the texture path), the four bilinear taps, and the
 // sun direction (through L, s_p, c_p, the texture path and t* = (n*+1) delta/2
 // with delta = texel / cos e).  Each partial below is the derivative of the
@@ -70,22 +82,35 @@ struct SunTrig {
   float se, ce, sa, ca, tan_e;
 };
 
-template <bool SPHERE, int TW, int MODE>
-__global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
-                                                      const float* __restrict__ gs,
-                                                      float* __restrict__ gh,
-                                                      double* __restrict__ gsun, int nbx,
-                                                      int nblocks) {
-  int i, j;
-  ray_coords<TW>(nbx, nblocks, i, j);
-  double ge = 0.0, ga = 0.0;
+template <bool SPHERE, int MODE, bool SAVED>
+__device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, int i, int j,
+                                            const float* __restrict__ gs,
+                                            const int* __restrict__ sample,
+                                            float* __restrict__ gh, double& ge, double& ga) {
   if (i < T.W && j < T.H) {
     const float g = gs[j * T.W + i];
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
-    unsigned n_lb = 0, n_smp = 0;
-    const RayResult res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp);
+    RayResult res;
+    if (SAVED) {
+      // the recorded sample, with the forward's own arithmetic: t rounded once
+      // from its index, u(t), the clearance key and its angle
+      const int n = sample[j * T.W + i];
+      res.valid = n >= 0 && g != 0.0f;
+      res.alpha = SS_INF;
+      if (res.valid) {
+        res.t = fmaf((float)n, MODE == SS_MODE_UNIFORM ? T.ustep : T.half_delta, T.half_delta);
+        res.u = t_to_u(r, res.t);
+        const Sample s0 = sample_at(r, T, res.t, res.u);
+        float num0, den0;
+        clearance_terms(r, res.t, s0.dh, num0, den0);
+        res.alpha = angle_of(tangent_key(num0, den0));
+      }
+    } else {
+      unsigned n_lb = 0, n_smp = 0;
+      res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp);
+    }
     const float dd = res.alpha * T.inv_rL;
     if (res.valid && g != 0.0f && fabsf(dd) < 1.0f) {
       const float t = res.t, u = res.u;
@@ -189,16 +214,55 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
       // t = texel (1/2 + k step) / cos e (every mode) grows with e; L(e, a)
       // on the unit sphere
       const double dte = (double)a_t * (double)t * (double)st.tan_e;
-      ge = dte + (double)a_Lx * (-(double)st.se * st.ca) + (double)a_Ly * (-(double)st.se * st.sa) +
-           (double)a_Lz * (double)st.ce;
-      ga = (double)a_Lx * (-(double)st.ce * st.sa) + (double)a_Ly * ((double)st.ce * st.ca);
+      ge += dte + (double)a_Lx * (-(double)st.se * st.ca) + (double)a_Ly * (-(double)st.se * st.sa) +
+            (double)a_Lz * (double)st.ce;
+      ga += (double)a_Lx * (-(double)st.ce * st.sa) + (double)a_Ly * ((double)st.ce * st.ca);
     }
+  }
+}
+
+// Each workgroup adds its sun gradient once (waves reduce through LDS), and
+// with a recorded forward, where a ray costs little, it takes four
+// consecutive ray blocks: the two fp64 sums every workgroup shares are then
+// hit by one atomic pair per 4096 rays instead of one per wavefront.  A
+// replaying adjoint keeps one block per workgroup for parallelism.
+template <bool SAVED>
+struct AdjBlocks {
+  static constexpr int n = SAVED ? 4 : 1;
+};
+
+template <bool SPHERE, int TW, int MODE, bool SAVED>
+__global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
+                                                      const float* __restrict__ gs,
+                                                      const int* __restrict__ sample,
+                                                      float* __restrict__ gh,
+                                                      double* __restrict__ gsun, int nbx,
+                                                      int nblocks) {
+  __shared__ double red[2][4];
+  double ge = 0.0, ga = 0.0;
+  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  for (int g = 0; g < AdjBlocks<SAVED>::n; ++g) {
+    const int vb = b * AdjBlocks<SAVED>::n + g;
+    if (vb >= nblocks) break;
+    int i, j;
+    coords_of<TW>(vb, nbx, i, j);
+    adjoint_ray<SPHERE, MODE, SAVED>(T, st, i, j, gs, sample, gh, ge, ga);
   }
   ge = wave_sum_f64(ge);
   ga = wave_sum_f64(ga);
-  if ((threadIdx.x & 63) == 0 && (ge != 0.0 || ga != 0.0)) {
-    atomicAdd(&gsun[0], ge);
-    atomicAdd(&gsun[1], ga);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = ge;
+    red[1][wave] = ga;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double se = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    const double sa = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    if (se != 0.0 || sa != 0.0) {
+      atomicAdd(&gsun[0], se);
+      atomicAdd(&gsun[1], sa);
+    }
   }
 }
 
@@ -219,85 +283,85 @@ void grid_for(const TileK& T, int ray_tile, int* nbx, int* nblocks) {
   *nblocks = bx * by;
 }
 
+template <bool SPHERE, int TW, int MODE>
+static void launch_fwd_m(const TileK& T, int flags, float* out, unsigned long long* counter,
+                         int* sample, int nbx, int nb, hipStream_t stream) {
+  dim3 grid(nb), block(256);
+  if (flags == FWD_COUNT)
+    hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, MODE, FWD_COUNT>), grid, block, 0, stream, T, out,
+                       counter, sample, nbx, nb);
+  else if (flags == FWD_SAVE)
+    hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, MODE, FWD_SAVE>), grid, block, 0, stream, T, out,
+                       counter, sample, nbx, nb);
+  else
+    hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, MODE, FWD_PLAIN>), grid, block, 0, stream, T, out,
+                       counter, sample, nbx, nb);
+}
+
 template <bool SPHERE, int TW>
-static hipError_t launch_fwd_tw(const TileK& T, int mode, bool count, float* out,
-                                unsigned long long* counter, hipStream_t stream) {
+static hipError_t launch_fwd_tw(const TileK& T, int mode, int flags, float* out,
+                                unsigned long long* counter, int* sample, hipStream_t stream) {
   int nbx, nb;
   grid_for(T, TW == 16 ? SS_TILE_16x4 : TW == 4 ? SS_TILE_4x16 : TW == 32 ? SS_TILE_32x2 : SS_TILE_8x8,
            &nbx, &nb);
   if (nb == 0) return hipSuccess;
-  dim3 grid(nb), block(256);
-  if (mode == SS_MODE_DP) {
-    if (count)
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_DP, true>), grid, block, 0, stream, T,
-                         out, counter, nbx, nb);
-    else
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_DP, false>), grid, block, 0, stream, T,
-                         out, counter, nbx, nb);
-  } else if (mode == SS_MODE_EXACT) {
-    if (count)
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_EXACT, true>), grid, block, 0, stream,
-                         T, out, counter, nbx, nb);
-    else
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_EXACT, false>), grid, block, 0,
-                         stream, T, out, counter, nbx, nb);
-  } else if (mode == SS_MODE_POINT) {
-    if (count)
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_POINT, true>), grid, block, 0, stream,
-                         T, out, counter, nbx, nb);
-    else
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_POINT, false>), grid, block, 0,
-                         stream, T, out, counter, nbx, nb);
-  } else {
-    if (count)
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_UNIFORM, true>), grid, block, 0, stream,
-                         T, out, counter, nbx, nb);
-    else
-      hipLaunchKernelGGL((shadow_kernel<SPHERE, TW, SS_MODE_UNIFORM, false>), grid, block, 0,
-                         stream, T, out, counter, nbx, nb);
+  switch (mode) {
+    case SS_MODE_EXACT: launch_fwd_m<SPHERE, TW, SS_MODE_EXACT>(T, flags, out, counter, sample, nbx, nb, stream); break;
+    case SS_MODE_POINT: launch_fwd_m<SPHERE, TW, SS_MODE_POINT>(T, flags, out, counter, sample, nbx, nb, stream); break;
+    case SS_MODE_UNIFORM: launch_fwd_m<SPHERE, TW, SS_MODE_UNIFORM>(T, flags, out, counter, sample, nbx, nb, stream); break;
+    default: launch_fwd_m<SPHERE, TW, SS_MODE_DP>(T, flags, out, counter, sample, nbx, nb, stream); break;
   }
   return hipGetLastError();
 }
 
 template <bool SPHERE>
-static hipError_t launch_fwd_s(const TileK& T, int mode, int ray_tile, bool count, float* out,
-                               unsigned long long* counter, hipStream_t stream) {
+static hipError_t launch_fwd_s(const TileK& T, int mode, int ray_tile, int flags, float* out,
+                               unsigned long long* counter, int* sample, hipStream_t stream) {
   switch (ray_tile) {
-    case SS_TILE_16x4: return launch_fwd_tw<SPHERE, 16>(T, mode, count, out, counter, stream);
-    case SS_TILE_4x16: return launch_fwd_tw<SPHERE, 4>(T, mode, count, out, counter, stream);
-    case SS_TILE_32x2: return launch_fwd_tw<SPHERE, 32>(T, mode, count, out, counter, stream);
-    default: return launch_fwd_tw<SPHERE, 8>(T, mode, count, out, counter, stream);
+    case SS_TILE_16x4: return launch_fwd_tw<SPHERE, 16>(T, mode, flags, out, counter, sample, stream);
+    case SS_TILE_4x16: return launch_fwd_tw<SPHERE, 4>(T, mode, flags, out, counter, sample, stream);
+    case SS_TILE_32x2: return launch_fwd_tw<SPHERE, 32>(T, mode, flags, out, counter, sample, stream);
+    default: return launch_fwd_tw<SPHERE, 8>(T, mode, flags, out, counter, sample, stream);
   }
 }
 
 hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, bool count,
-                          float* out, unsigned long long* counter, hipStream_t stream) {
-  return sphere ? launch_fwd_s<true>(T, mode, ray_tile, count, out, counter, stream)
-                : launch_fwd_s<false>(T, mode, ray_tile, count, out, counter, stream);
+                          float* out, unsigned long long* counter, int* sample,
+                          hipStream_t stream) {
+  const int flags = count ? FWD_COUNT : (sample ? FWD_SAVE : FWD_PLAIN);
+  return sphere ? launch_fwd_s<true>(T, mode, ray_tile, flags, out, counter, sample, stream)
+                : launch_fwd_s<false>(T, mode, ray_tile, flags, out, counter, sample, stream);
 }
 
 template <bool SPHERE, int MODE>
-static void adjoint_launch(const TileK& T, const SunTrig& st, const float* gs, float* gh,
-                           double* gsun, int nbx, int nb, hipStream_t stream) {
-  hipLaunchKernelGGL((adjoint_kernel<SPHERE, 8, MODE>), dim3(nb), dim3(256), 0, stream, T, st, gs,
-                     gh, gsun, nbx, nb);
+static void adjoint_launch(const TileK& T, const SunTrig& st, const float* gs, const int* sample,
+                           float* gh, double* gsun, int nbx, int nb, hipStream_t stream) {
+  if (sample)
+    hipLaunchKernelGGL((adjoint_kernel<SPHERE, 8, MODE, true>),
+                       dim3((nb + AdjBlocks<true>::n - 1) / AdjBlocks<true>::n), dim3(256), 0,
+                       stream, T, st, gs, sample, gh, gsun, nbx, nb);
+  else
+    hipLaunchKernelGGL((adjoint_kernel<SPHERE, 8, MODE, false>), dim3(nb), dim3(256), 0, stream, T,
+                       st, gs, sample, gh, gsun, nbx, nb);
 }
 
 template <bool SPHERE>
-static void adjoint_mode(const TileK& T, int mode, const SunTrig& st, const float* gs, float* gh,
-                         double* gsun, int nbx, int nb, hipStream_t stream) {
+static void adjoint_mode(const TileK& T, int mode, const SunTrig& st, const float* gs,
+                         const int* sample, float* gh, double* gsun, int nbx, int nb,
+                         hipStream_t stream) {
   if (mode == SS_MODE_EXACT)
-    adjoint_launch<SPHERE, SS_MODE_EXACT>(T, st, gs, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_EXACT>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
   else if (mode == SS_MODE_POINT)
-    adjoint_launch<SPHERE, SS_MODE_POINT>(T, st, gs, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_POINT>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
   else if (mode == SS_MODE_UNIFORM)
-    adjoint_launch<SPHERE, SS_MODE_UNIFORM>(T, st, gs, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_UNIFORM>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
   else
-    adjoint_launch<SPHERE, SS_MODE_DP>(T, st, gs, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_DP>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
 }
 
 hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
-                          const float* gs, float* gh, double* gsun, hipStream_t stream) {
+                          const float* gs, const int* sample, float* gh, double* gsun,
+                          hipStream_t stream) {
   SunTrig st;
   st.se = (float)sin(elev);
   st.ce = (float)cos(elev);
@@ -308,9 +372,9 @@ hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, do
   grid_for(T, SS_TILE_8x8, &nbx, &nb);
   if (nb == 0) return hipSuccess;
   if (sphere)
-    adjoint_mode<true>(T, mode, st, gs, gh, gsun, nbx, nb, stream);
+    adjoint_mode<true>(T, mode, st, gs, sample, gh, gsun, nbx, nb, stream);
   else
-    adjoint_mode<false>(T, mode, st, gs, gh, gsun, nbx, nb, stream);
+    adjoint_mode<false>(T, mode, st, gs, sample, gh, gsun, nbx, nb, stream);
   return hipGetLastError();
 }
 

@@ -112,6 +112,11 @@ def test_rejects_bad_arguments(L):
                                        0x500000, None) == L.SS_ERR_INVALID_ARG
     assert lib.ss_shadow_cast_counted(C.byref(t), C.byref(s), C.byref(p), 0x200000, None,
                                       None) == L.SS_ERR_INVALID_ARG
+    # the recorded forward and its adjoint need the record
+    assert lib.ss_shadow_cast_save(C.byref(t), C.byref(s), C.byref(p), 0x200000, None,
+                                   None) == L.SS_ERR_INVALID_ARG
+    assert lib.ss_shadow_cast_backward_saved(C.byref(t), C.byref(s), C.byref(p), None, 0x300000,
+                                             0x400000, 0x500000, None) == L.SS_ERR_INVALID_ARG
 
 
 def test_batched_validation(L):

@@ -1,0 +1,77 @@
+"""GPU tests of the recorded forward (ss_shadow_cast_save) and the adjoint
+that reads the record (ss_shadow_cast_backward_saved), in every mode: the
+forward is bit-identical to ss_shadow_cast, the recorded sample index equals
+the oracle's deciding sample on penumbra rays whose decisions are well clear of
+FP32 resolution, and the gradients equal the replaying adjoint's up to the
+order of the atomic sums."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from test_gpu_adjoint import well_conditioned
+
+pytestmark = pytest.mark.gpu
+
+R = 1737400.0
+RL = math.radians(0.267)
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import paper_2005_06671_amd as m
+    m.lib()
+    return m
+
+
+def rough(shape, seed, amp):
+    rng = np.random.default_rng(seed)
+    rows, width = shape
+    y, x = np.mgrid[0:rows, 0:width].astype(np.float64)
+    h = np.zeros(shape)
+    for k in range(6):
+        f = rng.uniform(0.01, 0.2)
+        th = rng.uniform(0, 2 * math.pi)
+        h += amp / (k + 1) * np.sin(f * (x * math.cos(th) + y * math.sin(th)) + rng.uniform(0, 6))
+    return h.astype(np.float32)
+
+
+MODES = [(0, 1.0), (1, 1.0), (1, 0.5), (2, 1.0), (3, 1.0)]
+CASES = [((200, 256), 20.0, R, 1.5, 0.7, 0.0), ((160, 176), 20.0, math.inf, 2.0, 2.3, 0.0),
+         ((256, 240), 15.0, R, 1.0, 4.1, 1500.0)]
+
+
+@pytest.mark.parametrize("mode,step", MODES)
+@pytest.mark.parametrize("shape,D,radius,e_deg,az,cap", CASES)
+def test_saved_forward_and_backward(ss, shape, D, radius, e_deg, az, cap, mode, step):
+    print("saved", shape, mode, step, flush=True)
+    h = rough(shape, shape[0] + 11, 80.0)
+    hd = torch.from_numpy(h).cuda()
+    e = math.radians(e_deg)
+    params = ss.Params(radius_m=radius, max_len_m=cap, mode=mode, uniform_step=step)
+    s_plain = ss.shadow_cast(hd, D, e, az, RL, params)
+    s_save, sample = ss.shadow_cast_save(hd, D, e, az, RL, params)
+    torch.cuda.synchronize()
+    assert torch.equal(s_plain.view(torch.int32), s_save.view(torch.int32))
+    # the recorded sample is the oracle's deciding sample on penumbra rays
+    # whose every decision is well conditioned
+    p = oracle.Params(shape[1], shape[0], D, radius, e, az, RL, max_len_m=cap, mode=mode,
+                      uniform_step=step)
+    s_or, _, tr = oracle.shadow(h, p, trace=True)
+    pen = (s_or.reshape(-1) > 0) & (s_or.reshape(-1) < 1)
+    mask = well_conditioned(tr) & pen
+    got = sample.cpu().numpy().reshape(-1)
+    assert mask.sum() > 100
+    bad = np.nonzero(got[mask] != tr.reshape(-1)["n"][mask])[0]
+    assert bad.size == 0, (bad.size, got[mask][bad[:5]], tr.reshape(-1)["n"][mask][bad[:5]])
+    assert np.all(got[s_or.reshape(-1) == 1.0] >= -1)
+    # gradients: recorded vs replayed
+    g = torch.from_numpy(np.random.default_rng(5).standard_normal(shape).astype(np.float32)).cuda()
+    gh1, gs1 = ss.shadow_cast_backward(hd, D, e, az, g, RL, params)
+    gh2, gs2 = ss.shadow_cast_backward_saved(hd, D, e, az, sample, g, RL, params)
+    torch.cuda.synchronize()
+    a, b = gh1.double(), gh2.double()
+    assert float((a - b).norm()) <= 1e-5 * max(float(a.norm()), 1e-30)
+    assert torch.allclose(gs1, gs2, rtol=1e-6, atol=1e-9 * float(gs1.abs().max()) + 1e-12)
