@@ -151,7 +151,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, counters_dir, out_dir):
         wb = sum(write.get(name, [0.0])) / max(1, len(write.get(name, []))) * 1024 * cal_w
         out["kernels"][name] = {"launches": len(fetch[name]), "fetch_bytes": fb,
                                 "write_bytes": wb}
-    dp = [k for k in out["kernels"] if "shadow_kernel<true, 8, 0, false>" in k]
+    dp = [k for k in out["kernels"] if "shadow_kernel<true, 8, 0, 0>" in k]
     if dp:
         k = out["kernels"][dp[0]]
         out["hbm_bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
@@ -516,7 +516,7 @@ def main():
     traffic = traffic_from_profile()
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                 "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic,
-                "kernel": "shadow_kernel<sphere, 8x8, descent>",
+                "kernel": "shadow_kernel<sphere, 8x8, descent, plain>",
                 "avg_launch_ms": avg_dp_ms, "lb_evals_per_ray": n_lb / (W * H),
                 "samples_per_ray": n_smp / (W * H),
                 "ops_model": {"lb": OPS_LB, "sample": OPS_SAMPLE, "ray": OPS_RAY}}
