@@ -79,13 +79,23 @@ typedef struct {
 /* One heightfield tile.  `maxmip` holds levels >= 1 of its maximum mipmap in
  * the packed layout below (built by ss_maxmip_build); `bound` holds its
  * tap-bound pyramid (built by ss_bound_build), read by SS_MODE_EXACT only and
- * may be NULL otherwise. */
+ * may be NULL otherwise.
+ *
+ * Ray window: rays start only at texels (i, j) with ray_x0 <= i < ray_x0 +
+ * ray_w and ray_y0 <= j < ray_y0 + ray_h, while they see the whole tile.  A
+ * tile made of a core plus a halo of neighbouring terrain (up to the ray cap
+ * toward the sun) gives the core's shadows as if the terrain went on past its
+ * edge; it is also how one tile splits over GPUs.  Per-ray buffers (d_shadow,
+ * d_sample, d_grad_shadow) are then [ray_h][ray_w]; d_grad_height stays
+ * [rows][width].  All four zero: the whole tile.  The window must lie inside
+ * the tile. */
 typedef struct {
   const float* height;     /* device, [rows][width] */
   const float* maxmip;     /* device, ss_maxmip_floats(width, rows) floats */
   int32_t width, rows;     /* >= 1 */
   double texel_m;          /* > 0 */
   const float* bound;      /* device, ss_bound_floats(width, rows) floats, or NULL */
+  int32_t ray_x0, ray_y0, ray_w, ray_h;  /* ray window, all 0 = whole tile */
 } ss_tile;
 
 /* ---- maximum mipmap (Sec. 3.2, "Maximum mipmaps") ------------------------ */

@@ -36,7 +36,9 @@ class SSParams(C.Structure):
 
 class SSTile(C.Structure):
     _fields_ = [("height", C.c_void_p), ("maxmip", C.c_void_p), ("width", C.c_int32),
-                ("rows", C.c_int32), ("texel_m", C.c_double), ("bound", C.c_void_p)]
+                ("rows", C.c_int32), ("texel_m", C.c_double), ("bound", C.c_void_p),
+                ("ray_x0", C.c_int32), ("ray_y0", C.c_int32), ("ray_w", C.c_int32),
+                ("ray_h", C.c_int32)]
 
 
 # Every exported symbol with (restype, argtypes); the CPU tests check that this

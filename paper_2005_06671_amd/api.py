@@ -119,10 +119,26 @@ def bound_unpack(b: torch.Tensor, width: int, rows: int) -> list:
     return out
 
 
-def _tile(h: torch.Tensor, mm: torch.Tensor, texel_m: float, bound=None) -> L.SSTile:
+def _tile(h: torch.Tensor, mm: torch.Tensor, texel_m: float, bound=None, window=None) -> L.SSTile:
+    """window = (x0, y0, w, h): rays start only in that rectangle (ss_tile)."""
     rows, width = h.shape
+    x0, y0, w, hh = (0, 0, 0, 0) if window is None else (int(v) for v in window)
     return L.SSTile(h.data_ptr(), mm.data_ptr(), width, rows, float(texel_m),
-                    bound.data_ptr() if bound is not None else None)
+                    bound.data_ptr() if bound is not None else None, x0, y0, w, hh)
+
+
+def _ray_shape(h: torch.Tensor, window) -> tuple:
+    """Shape of the per-ray buffers: the window's, or the tile's."""
+    if window is None:
+        return tuple(h.shape)
+    return (int(window[3]), int(window[2]))
+
+
+def _check_ray_buf(t: torch.Tensor, h: torch.Tensor, window, dtype, name: str) -> None:
+    if (not isinstance(t, torch.Tensor) or tuple(t.shape) != _ray_shape(h, window)
+            or t.dtype != dtype or not t.is_contiguous() or t.device != h.device):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape "
+                         f"{_ray_shape(h, window)} on {h.device}")
 
 
 def _bound_for(h, params, bound):
@@ -138,17 +154,19 @@ def _sun(elev: float, azim: float, ang_radius: float) -> L.SSSun:
 def shadow_cast(h: torch.Tensor, texel_m: float, elev: float, azim: float,
                 ang_radius: float = SUN_RADIUS_RAD, params: Params | None = None,
                 mm: torch.Tensor | None = None, out: torch.Tensor | None = None,
-                bound: torch.Tensor | None = None) -> torch.Tensor:
-    """Shadow factor s in [0, 1] for every texel of h (builds the mipmap if mm is
-    None, and in the exact mode the tap-bound pyramid if bound is None)."""
+                bound: torch.Tensor | None = None, window=None) -> torch.Tensor:
+    """Shadow factor s in [0, 1] for every texel of h, or of the ray window
+    (x0, y0, w, h) (builds the mipmap if mm is None, and in the exact mode the
+    tap-bound pyramid if bound is None)."""
     _dev_f32_2d(h)
     params = params or Params()
     if mm is None:
         mm = maxmip(h)
     bound = _bound_for(h, params, bound)
     if out is None:
-        out = torch.empty_like(h)
-    t = _tile(h, mm, texel_m, bound)
+        out = torch.empty(_ray_shape(h, window), dtype=torch.float32, device=h.device)
+    _check_ray_buf(out, h, window, torch.float32, "out")
+    t = _tile(h, mm, texel_m, bound, window)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast", L.lib().ss_shadow_cast(C.byref(t), C.byref(s), C.byref(p),
@@ -157,7 +175,7 @@ def shadow_cast(h: torch.Tensor, texel_m: float, elev: float, azim: float,
 
 
 def shadow_cast_counted(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=None, mm=None,
-                        out=None, bound=None):
+                        out=None, bound=None, window=None):
     """(s, [lower-bound evaluations, bilinear samples]) of one forward launch."""
     _dev_f32_2d(h)
     params = params or Params()
@@ -165,9 +183,10 @@ def shadow_cast_counted(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, param
         mm = maxmip(h)
     bound = _bound_for(h, params, bound)
     if out is None:
-        out = torch.empty_like(h)
+        out = torch.empty(_ray_shape(h, window), dtype=torch.float32, device=h.device)
+    _check_ray_buf(out, h, window, torch.float32, "out")
     cnt = torch.zeros(2, dtype=torch.int64, device=h.device)
-    t = _tile(h, mm, texel_m, bound)
+    t = _tile(h, mm, texel_m, bound, window)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast_counted",
@@ -177,10 +196,10 @@ def shadow_cast_counted(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, param
 
 
 def shadow_cast_backward(h, texel_m, elev, azim, grad_s, ang_radius=SUN_RADIUS_RAD, params=None,
-                         mm=None, grad_h=None, grad_sun=None, bound=None):
+                         mm=None, grad_h=None, grad_sun=None, bound=None, window=None):
     """Accumulates dL/dh (float32) and dL/d(elev, azim) (float64[2]) for upstream dL/ds."""
     _dev_f32_2d(h)
-    _dev_f32_2d(grad_s, "grad_s")
+    _check_ray_buf(grad_s, h, window, torch.float32, "grad_s")
     params = params or Params()
     if mm is None:
         mm = maxmip(h)
@@ -189,7 +208,7 @@ def shadow_cast_backward(h, texel_m, elev, azim, grad_s, ang_radius=SUN_RADIUS_R
         grad_h = torch.zeros_like(h)
     if grad_sun is None:
         grad_sun = torch.zeros(2, dtype=torch.float64, device=h.device)
-    t = _tile(h, mm, texel_m, bound)
+    t = _tile(h, mm, texel_m, bound, window)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast_backward",
@@ -200,7 +219,7 @@ def shadow_cast_backward(h, texel_m, elev, azim, grad_s, ang_radius=SUN_RADIUS_R
 
 
 def shadow_cast_save(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=None, mm=None,
-                     out=None, bound=None, sample=None):
+                     out=None, bound=None, sample=None, window=None):
     """(s, sample): s as shadow_cast, and each ray's deciding sample index (int32, -1 none)."""
     _dev_f32_2d(h)
     params = params or Params()
@@ -208,12 +227,12 @@ def shadow_cast_save(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=N
         mm = maxmip(h)
     bound = _bound_for(h, params, bound)
     if out is None:
-        out = torch.empty_like(h)
+        out = torch.empty(_ray_shape(h, window), dtype=torch.float32, device=h.device)
     if sample is None:
-        sample = torch.empty(h.shape, dtype=torch.int32, device=h.device)
-    elif sample.shape != h.shape or sample.dtype != torch.int32 or not sample.is_contiguous():
-        raise ValueError("sample must be a contiguous int32 tensor shaped like h")
-    t = _tile(h, mm, texel_m, bound)
+        sample = torch.empty(_ray_shape(h, window), dtype=torch.int32, device=h.device)
+    _check_ray_buf(out, h, window, torch.float32, "out")
+    _check_ray_buf(sample, h, window, torch.int32, "sample")
+    t = _tile(h, mm, texel_m, bound, window)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast_save",
@@ -223,12 +242,12 @@ def shadow_cast_save(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=N
 
 
 def shadow_cast_backward_saved(h, texel_m, elev, azim, sample, grad_s, ang_radius=SUN_RADIUS_RAD,
-                               params=None, mm=None, grad_h=None, grad_sun=None, bound=None):
+                               params=None, mm=None, grad_h=None, grad_sun=None, bound=None,
+                               window=None):
     """shadow_cast_backward from the record of shadow_cast_save (no replay)."""
     _dev_f32_2d(h)
-    _dev_f32_2d(grad_s, "grad_s")
-    if sample.shape != h.shape or sample.dtype != torch.int32 or not sample.is_contiguous():
-        raise ValueError("sample must be a contiguous int32 tensor shaped like h")
+    _check_ray_buf(grad_s, h, window, torch.float32, "grad_s")
+    _check_ray_buf(sample, h, window, torch.int32, "sample")
     params = params or Params()
     if mm is None:
         mm = maxmip(h)
@@ -237,7 +256,7 @@ def shadow_cast_backward_saved(h, texel_m, elev, azim, sample, grad_s, ang_radiu
         grad_h = torch.zeros_like(h)
     if grad_sun is None:
         grad_sun = torch.zeros(2, dtype=torch.float64, device=h.device)
-    t = _tile(h, mm, texel_m, bound)
+    t = _tile(h, mm, texel_m, bound, window)
     s = _sun(elev, azim, ang_radius)
     p = params.c()
     L.check("ss_shadow_cast_backward_saved",
@@ -258,49 +277,53 @@ class ShadowCast(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, h, elev, azim, texel_m, ang_radius, params):
+    def forward(ctx, h, elev, azim, texel_m, ang_radius, params, window=None):
         e = float(elev)
         a = float(azim)
         hd = h.detach().contiguous()
         mm = maxmip(hd)
         bound = _bound_for(hd, params, None)
-        s, sample = shadow_cast_save(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound)
+        s, sample = shadow_cast_save(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound,
+                                     window=window)
         ctx.save_for_backward(hd, mm, bound, sample)
-        ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim)
+        ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim, window)
         return s
 
     @staticmethod
     def backward(ctx, grad_s):
         hd, mm, bound, sample = ctx.saved_tensors
-        texel_m, e, a, ang_radius, params, elev, azim = ctx.cfg
+        texel_m, e, a, ang_radius, params, elev, azim, window = ctx.cfg
         g = grad_s.contiguous()
         gh, gsun = shadow_cast_backward_saved(hd, texel_m, e, a, sample, g, ang_radius, params,
-                                              mm=mm, bound=bound)
+                                              mm=mm, bound=bound, window=window)
         ge = gsun[0].to(elev.device) if isinstance(elev, torch.Tensor) else None
         ga = gsun[1].to(azim.device) if isinstance(azim, torch.Tensor) else None
-        return gh, ge, ga, None, None, None
+        return gh, ge, ga, None, None, None, None
 
 
-def shadow(h, elev, azim, texel_m, ang_radius=SUN_RADIUS_RAD, params: Params | None = None):
-    """Differentiable shadow factor (see ShadowCast)."""
+def shadow(h, elev, azim, texel_m, ang_radius=SUN_RADIUS_RAD, params: Params | None = None,
+           window=None):
+    """Differentiable shadow factor (see ShadowCast); window = (x0, y0, w, h)
+    limits the ray origins, the gradient still covers every height."""
     params = params or Params()
     if not isinstance(elev, torch.Tensor):
         elev = torch.tensor(float(elev), dtype=torch.float64)
     if not isinstance(azim, torch.Tensor):
         azim = torch.tensor(float(azim), dtype=torch.float64)
-    return ShadowCast.apply(h, elev, azim, texel_m, ang_radius, params)
+    return ShadowCast.apply(h, elev, azim, texel_m, ang_radius, params, window)
 
 
 # ---------------------------------------------------------------------------
 # Batched form
 # ---------------------------------------------------------------------------
 
-def _batch_structs(heights, mms, texels, suns):
+def _batch_structs(heights, mms, texels, suns, windows=None):
     nt = len(heights)
     tiles = (L.SSTile * max(1, nt))()
+    windows = windows or [None] * nt
     for k, (h, mm, tx) in enumerate(zip(heights, mms, texels)):
         _dev_f32_2d(h, f"heights[{k}]")
-        tiles[k] = _tile(h, mm, tx)
+        tiles[k] = _tile(h, mm, tx, None, windows[k])
     ns = len(suns)
     ss = (L.SSSun * max(1, ns))()
     for k, sun in enumerate(suns):
@@ -314,36 +337,38 @@ def batched_workspace_bytes(n_tiles: int, n_suns: int) -> int:
     return L.lib().ss_batched_workspace_bytes(n_tiles, n_suns)
 
 
-def _alloc_batch(heights, suns, outs, mms):
+def _alloc_batch(heights, suns, outs, mms, windows=None):
     dev = heights[0].device
+    windows = windows or [None] * len(heights)
     if mms is None:
         mms = [torch.empty(max(1, maxmip_floats(h.shape[1], h.shape[0])), dtype=torch.float32,
                            device=dev) for h in heights]
     if outs is None:
-        outs = [[torch.empty_like(h) for _ in suns] for h in heights]
+        outs = [[torch.empty(_ray_shape(h, w), dtype=torch.float32, device=dev) for _ in suns]
+                for h, w in zip(heights, windows)]
     ptrs = (C.c_void_p * max(1, len(heights) * len(suns)))()
     for t in range(len(heights)):
         for k in range(len(suns)):
             o = outs[t][k]
-            _dev_f32_2d(o, "out")
-            if o.shape != heights[t].shape:
-                raise ValueError("output shape differs from its tile")
+            _check_ray_buf(o, heights[t], windows[t], torch.float32, "out")
             ptrs[t * len(suns) + k] = o.data_ptr()
     ws = torch.empty(max(256, batched_workspace_bytes(len(heights), len(suns))), dtype=torch.uint8,
                      device=dev)
     return mms, outs, ptrs, ws
 
 
-def shadow_cast_batched(heights, texels, suns, params: Params | None = None, outs=None, mms=None):
-    """s for every (tile, sun): returns outs[t][k] (float32, shape of tile t).
+def shadow_cast_batched(heights, texels, suns, params: Params | None = None, outs=None, mms=None,
+                        windows=None):
+    """s for every (tile, sun): returns outs[t][k] (float32, shape of tile t or
+    of its ray window).
 
     Builds every tile's mipmap and runs one persistent launch over all items.
     """
     params = params or Params()
     if len(heights) == 0 or len(suns) == 0:
         return [[] for _ in heights]
-    mms, outs, ptrs, ws = _alloc_batch(heights, suns, outs, mms)
-    tiles, ss = _batch_structs(heights, mms, texels, suns)
+    mms, outs, ptrs, ws = _alloc_batch(heights, suns, outs, mms, windows)
+    tiles, ss = _batch_structs(heights, mms, texels, suns, windows)
     p = params.c()
     L.check("ss_shadow_cast_batched",
             L.lib().ss_shadow_cast_batched(tiles, len(heights), ss, len(suns), C.byref(p),
@@ -355,11 +380,13 @@ def shadow_cast_batched(heights, texels, suns, params: Params | None = None, out
 class BatchedPlan:
     """Captured HIP graph of the batched call for fixed buffers (tuned at creation)."""
 
-    def __init__(self, heights, texels, suns, params: Params | None = None, outs=None, mms=None):
+    def __init__(self, heights, texels, suns, params: Params | None = None, outs=None, mms=None,
+                 windows=None):
         self.params = params or Params()
         self.heights = list(heights)
-        self.mms, self.outs, self._ptrs, self.ws = _alloc_batch(self.heights, suns, outs, mms)
-        self._tiles, self._suns = _batch_structs(self.heights, self.mms, texels, suns)
+        self.mms, self.outs, self._ptrs, self.ws = _alloc_batch(self.heights, suns, outs, mms,
+                                                                windows)
+        self._tiles, self._suns = _batch_structs(self.heights, self.mms, texels, suns, windows)
         self._p = self.params.c()
         handle = C.c_void_p()
         L.check("ss_batched_plan_create",

@@ -187,6 +187,10 @@ static int32_t check_tile(const ss_tile* t, int mode) {
   if (!(t->texel_m > 0.0) || isinf(t->texel_m)) return SS_ERR_INVALID_ARG;
   if (ss_maxmip_floats(t->width, t->rows) > 0 && !t->maxmip) return SS_ERR_INVALID_ARG;
   if (mode == SS_MODE_EXACT && !t->bound) return SS_ERR_INVALID_ARG;
+  const int64_t x0 = t->ray_x0, y0 = t->ray_y0, w = t->ray_w, h = t->ray_h;
+  if (!(x0 == 0 && y0 == 0 && w == 0 && h == 0) &&
+      (x0 < 0 || y0 < 0 || w < 1 || h < 1 || x0 + w > t->width || y0 + h > t->rows))
+    return SS_ERR_INVALID_ARG;
   return SS_OK;
 }
 
@@ -211,6 +215,11 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
   K->W = W;
   K->H = H;
   K->L = L;
+  const bool whole = t->ray_w == 0 && t->ray_h == 0;
+  K->rx0 = whole ? 0 : t->ray_x0;
+  K->ry0 = whole ? 0 : t->ray_y0;
+  K->RW = whole ? W : t->ray_w;
+  K->RH = whole ? H : t->ray_h;
   for (int m = 0; m < L; ++m) {
     dims_of(W, H, m, &K->lw[m], &K->lh[m]);
     K->loff[m] = m == 0 ? 0 : (int)ss_maxmip_level_offset(W, H, m);

@@ -43,20 +43,21 @@ __global__ __launch_bounds__(256) void batched_kernel(const TileK* __restrict__ 
     float* out = outs[pair];
     const int nbx = pair_nbx[pair];
     const long long first = (item - item_start[pair]) * SS_ITEM_BLOCKS;
-    const long long nblk = (long long)nbx * ((T.H + 2 * TH - 1) / (2 * TH));
+    const long long nblk = (long long)nbx * ((T.RH + 2 * TH - 1) / (2 * TH));
     for (int g = 0; g < SS_ITEM_BLOCKS; ++g) {
       const long long blk = first + g;
       if (blk >= nblk) break;
       const int bxi = (int)(blk % nbx), byi = (int)(blk / nbx);
-      const int i = bxi * (2 * TW) + (wave & 1) * TW + lane % TW;
-      const int j = byi * (2 * TH) + (wave >> 1) * TH + lane / TW;
-      if (i < T.W && j < T.H) {
+      const int li = bxi * (2 * TW) + (wave & 1) * TW + lane % TW;
+      const int lj = byi * (2 * TH) + (wave >> 1) * TH + lane / TW;
+      if (li < T.RW && lj < T.RH) {
+        const int i = T.rx0 + li, j = T.ry0 + lj;
         const float hp = T.h[j * T.W + i];
         Ray<SPHERE> r;
         ray_init(T, i, j, hp, r);
         unsigned n_lb = 0, n_smp = 0;
         const float alpha = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp).alpha;
-        out[j * T.W + i] = disc_fraction(alpha, T);
+        out[lj * T.RW + li] = disc_fraction(alpha, T);
       }
     }
   }

@@ -16,6 +16,7 @@ struct TileK {
   const float* bnd;          // tap-bound pyramid level 0, [H][W] (exact mode only)
   const float* bmm;          // its levels >= 1, packed at loff[m] like mm
   int W, H, L;               // size and number of mip levels (incl. level 0)
+  int rx0, ry0, RW, RH;      // ray window: origins (rx0 + x, ry0 + y), x < RW, y < RH
   int lw[SS_MAXLEV], lh[SS_MAXLEV];
   int loff[SS_MAXLEV];       // float offset of level m >= 1 inside mm
   float texel;               // texel spacing on the tangent plane (m)

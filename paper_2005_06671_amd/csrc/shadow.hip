@@ -52,16 +52,17 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
                                                      int* __restrict__ sample, int nbx,
                                                      int nblocks) {
   constexpr bool COUNT = FLAGS == FWD_COUNT;
-  int i, j;
-  ray_coords<TW>(nbx, nblocks, i, j);
+  int li, lj;
+  ray_coords<TW>(nbx, nblocks, li, lj);
   unsigned n_lb = 0, n_smp = 0;
-  if (i < T.W && j < T.H) {
+  if (li < T.RW && lj < T.RH) {
+    const int i = T.rx0 + li, j = T.ry0 + lj;
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
     const RayResult res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp);
-    out[j * T.W + i] = disc_fraction(res.alpha, T);
-    if (FLAGS == FWD_SAVE) sample[j * T.W + i] = res.valid ? res.n : -1;
+    out[lj * T.RW + li] = disc_fraction(res.alpha, T);
+    if (FLAGS == FWD_SAVE) sample[lj * T.RW + li] = res.valid ? res.n : -1;
   }
   if (COUNT) {
     const unsigned a = wave_sum_u32(n_lb), b = wave_sum_u32(n_smp);
@@ -83,12 +84,13 @@ struct SunTrig {
 };
 
 template <bool SPHERE, int MODE, bool SAVED>
-__device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, int i, int j,
+__device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, int li, int lj,
                                             const float* __restrict__ gs,
                                             const int* __restrict__ sample,
                                             float* __restrict__ gh, double& ge, double& ga) {
-  if (i < T.W && j < T.H) {
-    const float g = gs[j * T.W + i];
+  if (li < T.RW && lj < T.RH) {
+    const int i = T.rx0 + li, j = T.ry0 + lj;
+    const float g = gs[lj * T.RW + li];
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
@@ -96,7 +98,7 @@ __device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, i
     if (SAVED) {
       // the recorded sample, with the forward's own arithmetic: t rounded once
       // from its index, u(t), the clearance key and its angle
-      const int n = sample[j * T.W + i];
+      const int n = sample[lj * T.RW + li];
       res.valid = n >= 0 && g != 0.0f;
       res.alpha = SS_INF;
       if (res.valid) {
@@ -277,8 +279,8 @@ static int tile_width_of(int code) {
 
 void grid_for(const TileK& T, int ray_tile, int* nbx, int* nblocks) {
   const int tw = tile_width_of(ray_tile), th = 64 / tw;
-  const int bx = (T.W + 2 * tw - 1) / (2 * tw);
-  const int by = (T.H + 2 * th - 1) / (2 * th);
+  const int bx = (T.RW + 2 * tw - 1) / (2 * tw);
+  const int by = (T.RH + 2 * th - 1) / (2 * th);
   *nbx = bx;
   *nblocks = bx * by;
 }

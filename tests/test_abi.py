@@ -149,6 +149,16 @@ def test_batched_validation(L):
                                       None) == L.SS_ERR_UNSUPPORTED
 
 
+def test_ray_window_validation(L):
+    lib = L.lib()
+    t, s, p = good(L)
+    for win in [(0, 0, 0, 5), (-1, 0, 4, 4), (0, 0, 65, 4), (60, 0, 5, 4), (0, 61, 4, 4),
+                (3, 3, 0, 2)]:
+        t2, _, _ = good(L)
+        t2.ray_x0, t2.ray_y0, t2.ray_w, t2.ray_h = win
+        assert cast(L, t2, s, p) == L.SS_ERR_INVALID_ARG, win
+
+
 def test_size_limits(L):
     """Each side <= 65536 and fewer than 2^30 texels (32-bit byte offsets)."""
     lib = L.lib()
