@@ -255,10 +255,30 @@ def leg_accuracy(ss, h, mm, D, suns, c):
              "tests_per_ray": sum(k[0] for k in cnt) / rays,
              "samples_per_ray": sum(k[1] for k in cnt) / rays,
              "launch_ms": t_ex}
+    desc = _err_stats(dp, u2)
+    point = _err_stats(pt, u2)
+    uni1 = _err_stats(u1, u2)
+    del dp, pt, u1, ex
+    # equal-error sweep: coarser uniform steps until the error passes the
+    # descent's, with their cost (the "same accuracy" comparison)
+    sweep = []
+    for step in (2.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0):
+        pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM,
+                       uniform_step=step)
+        ts, outs_u = [], []
+        for k, (e, a, r) in enumerate(suns):
+            o = ss.shadow_cast(h, D, e, a, r, pu, mm=mm)
+            ts += _timed(lambda: ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=o), 1)
+            outs_u.append(o)
+        st = _err_stats(torch.stack(outs_u), u2)
+        del outs_u
+        st.update({"step_texels": step, "launch_ms": sum(ts) / len(ts)})
+        sweep.append(st)
+        if st["mean_abs"] > desc["mean_abs"] and st["frac_gt_0.05"] > desc["frac_gt_0.05"]:
+            break
     return {"reference": "uniform stepping at delta/2 (dense half-texel grid), all suns",
-            "descent": _err_stats(dp, u2), "point_descent": _err_stats(pt, u2),
-            "uniform_1_texel": _err_stats(u1, u2),
-            "mean_s_dense": float(u2.mean())}, exact
+            "descent": desc, "point_descent": point, "uniform_1_texel": uni1,
+            "mean_s_dense": float(u2.mean()), "uniform_step_sweep": sweep}, exact
 
 
 def leg_schedules(ss, h, mm, D, suns):
@@ -292,6 +312,49 @@ def leg_schedules(ss, h, mm, D, suns):
         res[f"{m}_time_ratio_5553_over_555"] = res[f"{m}_5553"]["launch_ms"] / res[f"{m}_555"]["launch_ms"]
     res["uniform_100_over_point_555"] = res["uniform_100_steps"]["launch_ms"] / res["point_555"]["launch_ms"]
     return res
+
+
+def leg_gather(ss, dev, n_rays, src_floats, roof, iters=64, n_threads=1 << 21):
+    """Rate of incoherent 4-byte gathers (every lane of a wavefront on its own
+    cache line), from the library's gather probe (indices generated in the
+    kernel, eight loads in flight per lane) over a buffer the size of the
+    tile's heightfield plus mipmap, inside 1 MiB windows (L2-resident) and
+    16 KiB windows (L1-resident); against the descent's own gather rate (one
+    per lower bound, four per bilinear sample), whose 8 x 8 ray tiles keep
+    neighbouring lanes on shared cache lines."""
+    import torch
+    src = torch.rand(src_floats, device=dev)
+    out = torch.empty(n_threads, dtype=torch.float32, device=dev)
+    res = {}
+    for name, win in (("whole_buffer", 0), ("window_1MiB", 1 << 18), ("window_16KiB", 1 << 12)):
+        ss.probe_gather(src, win, iters, n_threads, out)
+        t = min(_timed(lambda: ss.probe_gather(src, win, iters, n_threads, out), 3))
+        res["incoherent_" + name + "_gathers_per_s"] = n_threads * iters / (t / 1e3)
+    res["descent_gathers_per_s"] = ((roof["lb_evals_per_ray"] + 4.0 * roof["samples_per_ray"])
+                                    * n_rays / (roof["avg_launch_ms"] / 1e3))
+    res["descent_over_incoherent_1MiB"] = (res["descent_gathers_per_s"]
+                                           / res["incoherent_window_1MiB_gathers_per_s"])
+    return res
+
+
+def cpu_uniform_baseline(h_np, params_or, seconds=5.0):
+    """The FP64 oracle's uniform stepping (1 texel) on a bounded random sample."""
+    import numpy as np
+    import oracle
+    threads = max(1, len(os.sched_getaffinity(0)))
+    rng = np.random.default_rng(4321)
+    n = 256 * threads
+    while True:
+        rays = rng.choice(h_np.size, size=min(h_np.size, n), replace=False)
+        t0 = time.perf_counter()
+        oracle.shadow_threaded(h_np, params_or, rays, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.6 * seconds or rays.size >= h_np.size:
+            break
+        n = int(rays.size * min(8.0, max(1.5, seconds / max(dt, 1e-3))))
+    return {"value": rays.size / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rays.size} random texels, first sun, uniform stepping at 1 texel, "
+                      f"{dt:.1f} s"}
 
 
 def leg_cold_maxmip(ss, h, mm, mm_bytes, reps=5):
@@ -527,11 +590,16 @@ def main():
               "frac": mm_bytes / (avg_mm_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
               "note": "64 MiB source is L2/MALL resident between steps (warm)"}
 
-    extras = {"step_ms_p10_p50_p90": _pct(step_ms), "launch_ms_p10_p50_p90": _pct(launch_ms)}
+    extras = {"step_ms_p10_p50_p90": _pct(step_ms), "launch_ms_p10_p50_p90": _pct(launch_ms),
+              "launch_ms_per_sun": [float(np.mean([ev_dp[i][k][0].elapsed_time(ev_dp[i][k][1])
+                                                   for i in range(args.steps)]))
+                                    for k in range(len(suns))]}
     if not args.no_extras:
         extras["accuracy_vs_dense"], extras["exact_mode"] = leg_accuracy(ss, h, mm, D, suns, c)
         maxmip["cold"] = leg_cold_maxmip(ss, h, mm, mm_bytes)
         extras["schedule_study"] = leg_schedules(ss, h, mm, D, suns)
+        extras["gather_ceiling"] = leg_gather(ss, dev, W * H, W * H + ss.maxmip_floats(W, H),
+                                              roofline)
         # uniform stepping, one texel per step, same suns, cap and exits
         pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
         for k, (e, a, r) in enumerate(suns[:1]):
@@ -586,6 +654,9 @@ def main():
         e, a, r = suns[0]
         po = oracle.Params(W, H, D, R_MOON, e, a, r, max_len_m=c["max_len"])
         cpu = cpu_baseline(h.cpu().numpy(), po)
+        if not args.no_extras:
+            extras["cpu_uniform_oracle"] = cpu_uniform_baseline(h.cpu().numpy(),
+                                                                po.replace(mode=1))
 
     line = {"metric": METRIC, "value": value, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,

@@ -217,6 +217,17 @@ int32_t ss_batched_plan_launch(ss_plan* plan, void* stream);
 int32_t ss_batched_plan_config(const ss_plan* plan, int32_t* ray_tile, int32_t* fuse_depth);
 int32_t ss_batched_plan_destroy(ss_plan* plan);
 
+/* ---- diagnostics --------------------------------------------------------- */
+
+/* Memory-system probe used to put the descent's gather rate in context (not
+ * part of the method): n_threads lanes (a multiple of 256) each sum `iters`
+ * floats (rounded up to a multiple of 8, eight loads in flight) of d_src at
+ * pseudo-random indices below the largest power of two
+ * <= n_floats, or, with window > 0 (a power of two <= n_floats), inside one
+ * window of that many floats per lane; d_out[n_threads] receives the sums. */
+int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t window, int32_t iters,
+                        float* d_out, int64_t n_threads, void* stream);
+
 /* Text for a status code (for SS_ERR_HIP: the last HIP error of this thread). */
 const char* ss_status_string(int32_t status);
 

@@ -267,6 +267,21 @@ def shadow_cast_backward_saved(h, texel_m, elev, azim, sample, grad_s, ang_radiu
     return grad_h, grad_sun
 
 
+def probe_gather(src: torch.Tensor, window: int = 0, iters: int = 64, n_threads: int = 1 << 21,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Memory-system gather probe (ss_probe_gather); returns the per-lane sums."""
+    if not src.is_cuda or src.dtype != torch.float32 or not src.is_contiguous():
+        raise ValueError("src must be a contiguous float32 CUDA tensor")
+    if out is None:
+        out = torch.empty(n_threads, dtype=torch.float32, device=src.device)
+    elif out.numel() < n_threads:
+        raise ValueError("out is too small")
+    L.check("ss_probe_gather", L.lib().ss_probe_gather(src.data_ptr(), src.numel(), int(window),
+                                                       int(iters), out.data_ptr(), int(n_threads),
+                                                       _stream(src.device)))
+    return out
+
+
 class ShadowCast(torch.autograd.Function):
     """s = shadow(h, elev, azim) with the hand-written adjoint kernel as backward.
 

@@ -336,6 +336,16 @@ static int32_t backward_common(const ss_tile* tile, const ss_sun* sun, const ss_
   return SS_OK;
 }
 
+extern "C" int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t window,
+                                   int32_t iters, float* d_out, int64_t n_threads, void* stream) {
+  if (!d_src || !d_out || n_floats < 1 || n_floats > (1LL << 32) || iters < 1) return SS_ERR_INVALID_ARG;
+  if (n_threads < 256 || n_threads % 256 != 0 || n_threads / 256 > 0x7fffffffLL) return SS_ERR_INVALID_ARG;
+  if (window < 0 || (window > 0 && ((window & (window - 1)) != 0 || window > n_floats)))
+    return SS_ERR_INVALID_ARG;
+  SS_HIP(launch_gather_probe(d_src, n_floats, window, iters, d_out, n_threads, (hipStream_t)stream));
+  return SS_OK;
+}
+
 extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun,
                                            const ss_params* params, const float* d_grad_shadow,
                                            float* d_grad_height, double* d_grad_sun, void* stream) {

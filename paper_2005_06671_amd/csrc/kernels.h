@@ -38,6 +38,10 @@ hipError_t launch_batched(const TileK* d_pairs, float* const* d_out_ptrs, const 
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream);
 int batched_workgroups(bool sphere, int mode, int ray_tile);
 
+// Gather throughput probe (measurement only).
+hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
+                               float* out, long long n_threads, hipStream_t stream);
+
 #define SS_ITEM_BLOCKS 4  // ray blocks (256 rays each) per queue item of the batched kernel
 
 }  // namespace ss

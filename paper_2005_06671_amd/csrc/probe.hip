@@ -1,0 +1,46 @@
+// Gather throughput probe for the memory system (a measurement tool, not part
+// of the method): every lane walks an xorshift sequence and sums the floats
+// it addresses, so no index array competes with the gathers for bandwidth.
+// Indices cover the largest power of two <= n floats, or a window of
+// `window` floats (a power of two) chosen per lane; iters is rounded up to a
+// multiple of 8.
+#include "kernels.h"
+
+namespace ss {
+
+__global__ __launch_bounds__(256) void gather_probe_kernel(const float* __restrict__ src,
+                                                           unsigned mask, unsigned wmask,
+                                                           unsigned nwin, int iters,
+                                                           float* __restrict__ out) {
+  const unsigned tid = blockIdx.x * 256u + threadIdx.x;
+  unsigned x = tid * 2654435761u + 12345u;
+  x ^= x >> 16;
+  const unsigned base = wmask ? ((x % nwin) * (wmask + 1u)) : 0u;
+  // eight independent loads in flight per lane
+  float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < iters; k += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      x ^= x << 13;
+      x ^= x >> 17;
+      x ^= x << 5;
+      const unsigned idx = wmask ? base + (x & wmask) : (x & mask);
+      acc[q] += src[idx];
+    }
+  }
+  out[tid] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
+                               float* out, long long n_threads, hipStream_t stream) {
+  unsigned long long p = 1;
+  while (p * 2 <= (unsigned long long)n_floats) p *= 2;
+  const unsigned mask = (unsigned)(p - 1);
+  const unsigned wmask = window > 0 ? (unsigned)(window - 1) : 0u;
+  const unsigned nwin = window > 0 ? (unsigned)(p / (unsigned long long)window) : 1u;
+  hipLaunchKernelGGL(gather_probe_kernel, dim3((unsigned)(n_threads / 256)), dim3(256), 0, stream,
+                     src, mask, wmask, nwin, iters, out);
+  return hipGetLastError();
+}
+
+}  // namespace ss
