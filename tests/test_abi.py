@@ -149,6 +149,15 @@ def test_batched_validation(L):
                                       None) == L.SS_ERR_UNSUPPORTED
 
 
+def test_probe_validation(L):
+    lib = L.lib()
+    ok = (0x100000, 1024, 0, 8, 0x200000, 256, None)
+    for k, bad in [(0, None), (1, 0), (2, 3), (2, 2048), (3, 0), (4, None), (5, 100)]:
+        args = list(ok)
+        args[k] = bad
+        assert lib.ss_probe_gather(*args) == L.SS_ERR_INVALID_ARG, (k, bad)
+
+
 def test_ray_window_validation(L):
     lib = L.lib()
     t, s, p = good(L)

@@ -116,3 +116,13 @@ def test_batched_windows(ss):
                 ref = ss.shadow_cast(hs[t], texels[t], e, a, r, p, window=wins[t])
                 torch.cuda.synchronize()
                 assert torch.equal(outs[t][k].view(torch.int32), ref.view(torch.int32)), (mode, t, k)
+
+
+def test_gather_probe_sums(ss):
+    """The memory probe reads only inside its buffer or window: over ones, every
+    lane sums exactly its rounded-up iteration count."""
+    src = torch.ones(1 << 20, device="cuda")
+    for win in (0, 1 << 12, 1 << 20):
+        out = ss.probe_gather(src, win, iters=12, n_threads=1 << 14)
+        torch.cuda.synchronize()
+        assert torch.all(out == 16.0), win
