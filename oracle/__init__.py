@@ -9,6 +9,7 @@ gcc into ``liboracle.so`` and called through ctypes; the reference gradient is
 torch float64 autograd (``grad_ref.py``).
 """
 from .core import (  # noqa: F401
-    Params, build, load, maxmip_levels, maxmip, shadow, shadow_threaded, alternatives,
+    Params, build, load, maxmip_levels, maxmip, shadow, shadow_threaded, shadow_points,
+    alternatives,
     disc_fraction, schedule, ray_consts, probe, path_cells, tap_bound, TRACE_DTYPE,
 )

@@ -69,6 +69,9 @@ def load():
         lib.or_shadow.argtypes = [C.c_void_p, P(_Params), C.c_void_p, C.c_int64, C.c_void_p,
                                   C.c_void_p, C.c_void_p]
         lib.or_shadow.restype = C.c_int32
+        lib.or_shadow_points.argtypes = [C.c_void_p, P(_Params), C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]
+        lib.or_shadow_points.restype = C.c_int32
         lib.or_alternatives.argtypes = [C.c_void_p, P(_Params), C.c_int64, C.c_double,
                                         C.c_double, C.c_double, C.c_double, C.c_void_p,
                                         C.c_int32]
@@ -224,6 +227,25 @@ def shadow(h: np.ndarray, p: Params, rays=None, trace: bool = False, _c=None):
         alpha = alpha.reshape(rows, width)
         if trace:
             tr = tr.reshape(rows, width)
+    return (s, alpha, tr) if trace else (s, alpha)
+
+
+def shadow_points(h: np.ndarray, p: Params, xy, trace: bool = False):
+    """s (float64) for shadow rays from surface points xy[k] = (qx, qy) in
+    continuous texel coordinates; the origin height is the bilinear terrain."""
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    rows, width = h.shape
+    assert (p.width, p.rows) == (width, rows)
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    n = xy.shape[0]
+    s = np.empty(n, dtype=np.float64)
+    alpha = np.empty(n, dtype=np.float64)
+    tr = np.empty(n, dtype=TRACE_DTYPE) if trace else None
+    pc = p.c()
+    rc = load().or_shadow_points(_ctx(h).ptr, C.byref(pc), xy.ctypes.data, n, s.ctypes.data,
+                                 alpha.ctypes.data, tr.ctypes.data if trace else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the points ({rc})")
     return (s, alpha, tr) if trace else (s, alpha)
 
 

@@ -183,14 +183,22 @@ void or_setup(setup_t* s, const or_ctx* c, const or_params* p) {
 /* ------------------------------------------------------------------ */
 
 void or_ray_init(ray_t* r, const setup_t* s, int i, int j) {
-  memset(r, 0, sizeof(*r));
-  r->s = s;
+  const or_ctx* c = s->c;
+  or_ray_init_at(r, s, i + 0.5, j + 0.5, c ? (double)c->level[0][(int64_t)j * c->W + i] : 0.0);
   r->i = i;
   r->j = j;
-  const or_ctx* c = s->c;
-  r->hp = c ? (double)c->level[0][(int64_t)j * c->W + i] : 0.0;
-  double X = (i + 0.5 - 0.5 * s->p->width) * s->D;
-  double Y = (j + 0.5 - 0.5 * s->p->rows) * s->D;
+}
+
+/* A ray from the surface point above continuous texel coordinates (qx, qy)
+ * at height hp (texel centres: (i + 1/2, j + 1/2) and the texel's height). */
+void or_ray_init_at(ray_t* r, const setup_t* s, double qx, double qy, double hp) {
+  memset(r, 0, sizeof(*r));
+  r->s = s;
+  r->i = (int)floor(qx);
+  r->j = (int)floor(qy);
+  r->hp = hp;
+  double X = (qx - 0.5 * s->p->width) * s->D;
+  double Y = (qy - 0.5 * s->p->rows) * s->D;
   const double* L = s->Lv;
   if (s->planar) {
     r->n[0] = 0.0;
@@ -668,6 +676,42 @@ int32_t or_shadow(const or_ctx* c, const or_params* p, const int64_t* rays, int6
     if (lin < 0 || lin >= (int64_t)c->W * c->H) return -2;
     ray_t r;
     or_ray_init(&r, &s, (int)(lin % c->W), (int)(lin / c->W));
+    or_trace tr;
+    double alpha;
+    if (p->mode == 1)
+      alpha = shadow_uniform(&r, p->uniform_step * s.delta, &tr);
+    else if (p->mode == 2)
+      alpha = shadow_uniform(&r, 0.5 * s.delta, &tr);
+    else if (p->mode == 3)
+      alpha = shadow_runs(&r, point_segment, &tr);
+    else
+      alpha = shadow_dp(&r, &tr);
+    double sv = 1.0;
+    if (isfinite(alpha)) {
+      double d = alpha / p->ang_radius_rad;
+      if (d < -1.0) d = -1.0;
+      if (d > 1.0) d = 1.0;
+      sv = or_disc_fraction(d);
+    }
+    if (s_out) s_out[k] = sv;
+    if (alpha_out) alpha_out[k] = alpha;
+    if (trace_out) trace_out[k] = tr;
+  }
+  return 0;
+}
+
+/* Shadow rays from arbitrary surface points: origin (qx, qy) in continuous
+ * texel coordinates (inside the tile), height the bilinear terrain there. */
+int32_t or_shadow_points(const or_ctx* c, const or_params* p, const double* xy, int64_t n,
+                         double* s_out, double* alpha_out, or_trace* trace_out) {
+  if (!c || !p || p->width != c->W || p->rows != c->H) return -1;
+  setup_t s;
+  or_setup(&s, c, p);
+  for (int64_t k = 0; k < n; ++k) {
+    double qx = xy[2 * k], qy = xy[2 * k + 1];
+    if (!or_inside(&s, qx, qy)) return -2;
+    ray_t r;
+    or_ray_init_at(&r, &s, qx, qy, or_bilinear(&s, qx, qy));
     or_trace tr;
     double alpha;
     if (p->mode == 1)

@@ -73,6 +73,11 @@ void or_ctx_copy_maxmip(const or_ctx* c, float* out);
 
 /* Shadow factor for n_rays texels (linear index j*width+i; NULL = all texels
  * in order).  s_out[k] in [0,1]; alpha_out and trace_out may be NULL. */
+/* Shadow rays from n surface points xy[2k], xy[2k+1] (continuous texel
+ * coordinates inside the tile; the origin height is the bilinear terrain
+ * there).  Returns -2 if a point lies outside. */
+int32_t or_shadow_points(const or_ctx* c, const or_params* p, const double* xy, int64_t n,
+                         double* s_out, double* alpha_out, or_trace* trace_out);
 int32_t or_shadow(const or_ctx* c, const or_params* p, const int64_t* rays, int64_t n_rays,
                   double* s_out, double* alpha_out, or_trace* trace_out);
 

@@ -48,6 +48,7 @@ typedef struct {
 
 void or_setup(setup_t* s, const or_ctx* c, const or_params* p);
 void or_ray_init(ray_t* r, const setup_t* s, int i, int j);
+void or_ray_init_at(ray_t* r, const setup_t* s, double qx, double qy, double hp);
 void or_ray_point(const ray_t* r, double t, double* qx, double* qy, double* Ht);
 double or_t_on_line(const ray_t* r, int axis, double g);
 int or_motion_sign(const ray_t* r, int axis);
