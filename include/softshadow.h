@@ -169,6 +169,17 @@ int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun, const ss
                                 const float* d_grad_shadow, float* d_grad_height,
                                 double* d_grad_sun, void* stream);
 
+/* Shadow factor at n arbitrary surface points: d_xy holds n (x, y) float pairs
+ * in continuous texel coordinates (texel i covers [i, i+1); 8-byte aligned),
+ * each ray starts on the bilinear terrain there (Sec. 3.4's sampling) and runs
+ * the chosen mode exactly as a texel-centre ray does; d_shadow[n] receives s.
+ * Points outside the tile are clamped to its edge.  The ray window is
+ * ignored.  Texel centres (i + 1/2, j + 1/2) give ss_shadow_cast's values.
+ * This is the call a view-ray caster feeds (Sec. 4: shadows at the visible
+ * surface points of a frame). */
+int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                         const float* d_xy, int64_t n, float* d_shadow, void* stream);
+
 /* Forward that also records, for every ray, the index n of its deciding
  * sample (the one whose clearance gave s): t = delta/2 + n * step with
  * step = delta/2, or the uniform step in SS_MODE_UNIFORM; -1 when no sample

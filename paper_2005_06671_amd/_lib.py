@@ -76,6 +76,8 @@ SIGNATURES = {
     "ss_batched_plan_config": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32),
                                            C.POINTER(C.c_int32)]),
     "ss_batched_plan_destroy": (C.c_int32, [C.c_void_p]),
+    "ss_shadow_points": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
+                                     C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ss_probe_gather": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
                                     C.c_int64, C.c_void_p]),
     "ss_status_string": (C.c_char_p, [C.c_int32]),

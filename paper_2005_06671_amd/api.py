@@ -267,6 +267,31 @@ def shadow_cast_backward_saved(h, texel_m, elev, azim, sample, grad_s, ang_radiu
     return grad_h, grad_sun
 
 
+def shadow_points(h: torch.Tensor, texel_m: float, elev: float, azim: float, xy: torch.Tensor,
+                  ang_radius: float = SUN_RADIUS_RAD, params: Params | None = None,
+                  mm: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                  bound: torch.Tensor | None = None) -> torch.Tensor:
+    """s at surface points xy [n, 2] (float32 CUDA, continuous texel coordinates)."""
+    _dev_f32_2d(h)
+    if (not isinstance(xy, torch.Tensor) or xy.dim() != 2 or xy.shape[1] != 2 or not xy.is_cuda
+            or xy.dtype != torch.float32 or not xy.is_contiguous()):
+        raise ValueError("xy must be a contiguous float32 CUDA tensor [n, 2]")
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
+    n = xy.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=h.device)
+    t = _tile(h, mm, texel_m, bound)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_points",
+            L.lib().ss_shadow_points(C.byref(t), C.byref(s), C.byref(p), xy.data_ptr(), n,
+                                     out.data_ptr(), _stream(h.device)))
+    return out
+
+
 def probe_gather(src: torch.Tensor, window: int = 0, iters: int = 64, n_threads: int = 1 << 21,
                  out: torch.Tensor | None = None) -> torch.Tensor:
     """Memory-system gather probe (ss_probe_gather); returns the per-lane sums."""

@@ -336,6 +336,23 @@ static int32_t backward_common(const ss_tile* tile, const ss_sun* sun, const ss_
   return SS_OK;
 }
 
+extern "C" int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun,
+                                    const ss_params* params, const float* d_xy, int64_t n,
+                                    float* d_shadow, void* stream) {
+  Resolved rp;
+  int32_t rc = resolve_params(params, &rp);
+  if (rc) return rc;
+  if ((rc = check_tile(tile, rp.mode))) return rc;
+  if ((rc = check_sun(sun))) return rc;
+  if (n < 0 || (n > 0 && (!d_xy || !d_shadow))) return SS_ERR_INVALID_ARG;
+  if (n == 0 || tile->width == 0 || tile->rows == 0) return n == 0 ? SS_OK : SS_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(d_xy) & 7) != 0) return SS_ERR_INVALID_ARG;
+  TileK K;
+  if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
+  SS_HIP(launch_points(K, rp.sphere, rp.mode, d_xy, n, d_shadow, (hipStream_t)stream));
+  return SS_OK;
+}
+
 extern "C" int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t window,
                                    int32_t iters, float* d_out, int64_t n_threads, void* stream) {
   if (!d_src || !d_out || n_floats < 1 || n_floats > (1LL << 32) || iters < 1) return SS_ERR_INVALID_ARG;

@@ -21,8 +21,10 @@ __device__ __forceinline__ float ss_sqrt(float x) { return __builtin_amdgcn_sqrt
 
 template <bool SPHERE>
 struct Ray {
-  int i, j;
-  float hp;          // origin height
+  int i, j;          // texel holding the origin
+  float ox, oy;      // origin minus that texel's centre, in texels (-0 at centres)
+  float hp;          // reference height: relative heights are taken from it
+  float dz;          // origin height above hp (-0 at centres, whose height is hp)
   float Kx, Ky;      // texture-space velocity per unit u (texels)
   float invKx, invKy;
   float c;           // projective constant: u = t / (1 + c t)
@@ -34,19 +36,28 @@ struct Ray {
   int sx, sy;        // direction of travel along columns / rows
 };
 
+// Ray from the surface point at texel (i, j)'s centre plus (ox, oy) texels,
+// at height hp + dz.  Positions are taken relative to the texel centre and
+// shifted by (ox, oy); heights relative to hp, a stored height, with the
+// origin dz above it.  At centres ox = oy = dz = -0, which every sum below
+// drops exactly, so those rays compute as if the terms were absent.
 template <bool SPHERE>
-__device__ __forceinline__ void ray_init(const TileK& T, int i, int j, float hp, Ray<SPHERE>& r) {
+__device__ __forceinline__ void ray_init(const TileK& T, int i, int j, float hp, Ray<SPHERE>& r,
+                                         float ox = -0.0f, float oy = -0.0f, float dz = -0.0f) {
   r.i = i;
   r.j = j;
+  r.ox = ox;
+  r.oy = oy;
   r.hp = hp;
-  const float X = ((float)i + 0.5f - 0.5f * (float)T.W) * T.texel;
-  const float Y = ((float)j + 0.5f - 0.5f * (float)T.H) * T.texel;
+  r.dz = dz;
+  const float X = ((float)i + 0.5f + ox - 0.5f * (float)T.W) * T.texel;
+  const float Y = ((float)j + 0.5f + oy - 0.5f * (float)T.H) * T.texel;
   if (SPHERE) {
     // n = (a, b, 1)/g with a = X/R, b = Y/R, g = |(a, b, 1)|; rho = R (1 + h_p/R)
     const float a = X * T.invR, b = Y * T.invR;
     const float g = sqrtf(1.0f + a * a + b * b);
     const float ig = 1.0f / g;
-    const float r1 = 1.0f + hp * T.invR;
+    const float r1 = 1.0f + (hp + dz) * T.invR;
     r.sp = (a * T.Lx + b * T.Ly + T.Lz) * ig;
     const float cx = b * T.Lz - T.Ly, cy = T.Lx - a * T.Lz, cz = a * T.Ly - b * T.Lx;
     r.cp = sqrtf(cx * cx + cy * cy + cz * cz) * ig;
@@ -81,10 +92,10 @@ __device__ __forceinline__ void ray_init(const TileK& T, int i, int j, float hp,
   r.invKy = r.sy ? 1.0f / r.Ky : SS_INF;
   // leaving the tile: first boundary in the direction of travel
   float ux = SS_INF, uy = SS_INF;
-  if (r.sx > 0) ux = ((float)(T.W - i) - 0.5f) / r.Kx;
-  if (r.sx < 0) ux = ((float)(-i) - 0.5f) / r.Kx;
-  if (r.sy > 0) uy = ((float)(T.H - j) - 0.5f) / r.Ky;
-  if (r.sy < 0) uy = ((float)(-j) - 0.5f) / r.Ky;
+  if (r.sx > 0) ux = ((float)(T.W - i) - 0.5f - ox) / r.Kx;
+  if (r.sx < 0) ux = ((float)(-i) - 0.5f - ox) / r.Kx;
+  if (r.sy > 0) uy = ((float)(T.H - j) - 0.5f - oy) / r.Ky;
+  if (r.sy < 0) uy = ((float)(-j) - 0.5f - oy) / r.Ky;
   r.uexit = fminf(ux, uy);
 }
 
@@ -98,15 +109,16 @@ __device__ __forceinline__ float t_to_u(const Ray<SPHERE>& r, float t) {
   return SPHERE ? t * ss_rcp(1.0f + r.c * t) : t;
 }
 
-// Tip height above the origin height: |p + t L| - |p| (sphere), t L_z (plane).
+// Tip height above the reference height hp: the rise above the origin,
+// |p + t L| - |p| (sphere) or t L_z (plane), plus the origin's dz.
 template <bool SPHERE>
 __device__ __forceinline__ float tip_rise(const Ray<SPHERE>& r, const TileK& T, float t) {
   if (SPHERE) {
     const float x = t * r.invrho;
     const float q = 2.0f * r.sp + x;
-    return t * q * ss_rcp(ss_sqrt(1.0f + x * q) + 1.0f);
+    return t * q * ss_rcp(ss_sqrt(1.0f + x * q) + 1.0f) + r.dz;
   }
-  return t * T.Lz;
+  return t * T.Lz + r.dz;
 }
 
 // The same tip height at the texture parameter u (t = u / A, A = 1 - c u):
@@ -120,9 +132,9 @@ __device__ __forceinline__ float tip_rise_u(const Ray<SPHERE>& r, const TileK& T
     const float v = u * r.invrho;
     const float P = fmaf(r.sp2, A, v);
     const float S = ss_sqrt(fmaf(A, A, v * P));
-    return u * P * ss_rcp((S + A) * A);
+    return u * P * ss_rcp((S + A) * A) + r.dz;
   }
-  return u * T.Lz;
+  return u * T.Lz + r.dz;
 }
 
 __device__ __forceinline__ const float* level_ptr(const TileK& T, int m) {
@@ -180,7 +192,7 @@ struct Sample {
 template <bool SPHERE>
 __device__ __forceinline__ Sample sample_at(const Ray<SPHERE>& r, const TileK& T, float t, float u) {
   Sample s;
-  const float dx = r.Kx * u, dy = r.Ky * u;
+  const float dx = fmaf(r.Kx, u, r.ox), dy = fmaf(r.Ky, u, r.oy);
   const float flx = floorf(dx), fly = floorf(dy);
   s.fx = dx - flx;
   s.fy = dy - fly;
@@ -196,6 +208,23 @@ __device__ __forceinline__ Sample sample_at(const Ray<SPHERE>& r, const TileK& T
                    s.fy * ((1.0f - s.fx) * h01 + s.fx * h11);
   s.dh = tip_rise(r, T, t) - hb;
   return s;
+}
+
+// Height of the bilinear terrain at continuous texel coordinates (qx, qy)
+// above the reference height ref (texel i covers [i, i+1); taps clamp to the
+// edge, as for the samples).  Differences of nearby heights are exact in
+// FP32, so the result carries no rounding of the absolute height.
+__device__ __forceinline__ float terrain_above(const TileK& T, float qx, float qy, float ref) {
+  const float x = qx - 0.5f, y = qy - 0.5f;
+  const float flx = floorf(x), fly = floorf(y);
+  const float fx = x - flx, fy = y - fly;
+  const int x0 = (int)flx, y0 = (int)fly;
+  const unsigned xa = (unsigned)min(max(x0, 0), T.W - 1), xb = (unsigned)min(max(x0 + 1, 0), T.W - 1);
+  const unsigned ya = (unsigned)min(max(y0, 0), T.H - 1), yb = (unsigned)min(max(y0 + 1, 0), T.H - 1);
+  const unsigned W = (unsigned)T.W;
+  const float h00 = T.h[idx2(ya, W, xa)] - ref, h10 = T.h[idx2(ya, W, xb)] - ref;
+  const float h01 = T.h[idx2(yb, W, xa)] - ref, h11 = T.h[idx2(yb, W, xb)] - ref;
+  return (1.0f - fy) * ((1.0f - fx) * h00 + fx * h10) + fy * ((1.0f - fx) * h01 + fx * h11);
 }
 
 // Visible part of the sun disc above a chord at d disc radii below its centre
@@ -256,12 +285,12 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   // path moves forward or not at all)
   const int ex = r.Kx >= 0.0f ? 1 : 0, ey = r.Ky >= 0.0f ? 1 : 0;
   // top level: walk the level-m texels crossed for u in [ua, ub]
-  int cx = (r.i >> m) + (int)floorf(ldexpf((float)(r.i & (S - 1)) + 0.5f + r.Kx * ua, -m));
-  int cy = (r.j >> m) + (int)floorf(ldexpf((float)(r.j & (S - 1)) + 0.5f + r.Ky * ua, -m));
+  int cx = (r.i >> m) + (int)floorf(ldexpf((float)(r.i & (S - 1)) + 0.5f + r.ox + r.Kx * ua, -m));
+  int cy = (r.j >> m) + (int)floorf(ldexpf((float)(r.j & (S - 1)) + 0.5f + r.oy + r.Ky * ua, -m));
   // those grid lines relative to the origin texel centre, in texels; they
   // are half-integers, exact in FP32, and move by +-2^m per step
-  float gx = (float)(((cx + ex) << m) - r.i) - 0.5f;
-  float gy = (float)(((cy + ey) << m) - r.j) - 0.5f;
+  float gx = (float)(((cx + ex) << m) - r.i) - 0.5f - r.ox;
+  float gy = (float)(((cy + ey) << m) - r.j) - 0.5f - r.oy;
   const float stx = (float)(r.sx * S), sty = (float)(r.sy * S);
   const Level Ltop = level_of(T, m);
   const unsigned lwm = (unsigned)T.lw[m], lhm = (unsigned)T.lh[m];
@@ -308,8 +337,8 @@ __device__ __forceinline__ void descend_run(const TileK& T, const Ray<SPHERE>& r
   // leaves its piece empty.
   const int bfx = 1 - ex, bfy = 1 - ey;  // child bits before the mid-lines
   // parent's low edge relative to the origin texel centre, in texels
-  float fx = (float)((bx << m) - r.i) - 0.5f;
-  float fy = (float)((by << m) - r.j) - 0.5f;
+  float fx = (float)((bx << m) - r.i) - 0.5f - r.ox;
+  float fy = (float)((by << m) - r.j) - 0.5f - r.oy;
   for (int lv = m; lv > 0; --lv) {
     const int half = 1 << (lv - 1);
     const float fh = (float)half;
@@ -429,8 +458,8 @@ __device__ __forceinline__ void point_run(const TileK& T, const Ray<SPHERE>& r, 
       const float t = (float)(a + kk + 1) * T.half_delta;
       const float u = t_to_u(r, t);
       // texel under the tip (positions before the edge are >= 0 by construction)
-      const int cx = (int)floorf((float)r.i + 0.5f + r.Kx * u) >> m;
-      const int cy = (int)floorf((float)r.j + 0.5f + r.Ky * u) >> m;
+      const int cx = (int)floorf((float)r.i + 0.5f + r.ox + r.Kx * u) >> m;
+      const int cy = (int)floorf((float)r.j + 0.5f + r.oy + r.Ky * u) >> m;
       const bool ok = u < r.uexit && (unsigned)cx < (unsigned)T.lw[m] && (unsigned)cy < (unsigned)T.lh[m];
       const float v = tip_rise(r, T, t) - (level_at(Lm, cx, cy) - r.hp);
       n_lb += ok ? 1u : 0u;
@@ -471,8 +500,9 @@ __device__ __forceinline__ void point_run(const TileK& T, const Ray<SPHERE>& r, 
 
 // True when every sample at ray length >= t clears the angle whose tangent is
 // need_tan (an angle in (-pi/2, pi/2)), given that no terrain rises above
-// `top` (relative to h_p, >= 0): the clearance of the point at that height
-// below the tip grows with t on the plane and on the sphere.  Used for the
+// `top` (relative to the reference height hp, and at least the origin's dz,
+// i.e. not below the origin): the clearance of the point at that height below
+// the tip grows with t on the plane and on the sphere.  Used for the
 // result-invariant early exits.
 template <bool SPHERE>
 __device__ __forceinline__ bool clears(const Ray<SPHERE>& r, const TileK& T, float t, float top,
@@ -648,20 +678,22 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
     const float u = t_to_u(r, t);
     if (!(u < r.uexit)) break;
     // texel under sample n (rounding past the edge is clamped)
-    const int ix = min(max((int)floorf((float)r.i + 0.5f + r.Kx * u), 0), T.W - 1);
-    const int iy = min(max((int)floorf((float)r.j + 0.5f + r.Ky * u), 0), T.H - 1);
+    const int ix = min(max((int)floorf((float)r.i + 0.5f + r.ox + r.Kx * u), 0), T.W - 1);
+    const int iy = min(max((int)floorf((float)r.j + 0.5f + r.oy + r.Ky * u), 0), T.H - 1);
     const int cx = ix >> m, cy = iy >> m;
     bool skip = false;
     if (T.prune) {
       n_tst++;
-      const float top = fmaxf(bound_at(T, m, cx, cy) - r.hp, 0.0f);
+      // relative to the origin the bound must be at least 0 (see clears)
+      const float b0 = fmaxf(bound_at(T, m, cx, cy) - r.hp, 0.0f);
+      const float top = r.dz > b0 ? r.dz : b0;
       skip = clears(r, T, t, top, need);
     }
     if (skip) {
       // first grid sample at or past the texel's exit (a sample a rounding
       // error past the exit is still under the bound's half-texel margin)
-      const float ux = ((float)(((cx + ex) << m) - r.i) - 0.5f) * r.invKx;
-      const float uy = ((float)(((cy + ey) << m) - r.j) - 0.5f) * r.invKy;
+      const float ux = ((float)(((cx + ex) << m) - r.i) - 0.5f - r.ox) * r.invKx;
+      const float uy = ((float)(((cy + ey) << m) - r.j) - 0.5f - r.oy) * r.invKy;
       const float tb = u_to_t(r, fminf(fminf(ux, uy), uend));
       const float nb = ceilf(tb * T.two_over_delta) - 1.0f;
       n = max(n + 1, (int)fminf(nb, 16777216.0f));
@@ -696,7 +728,8 @@ template <bool SPHERE, int MODE>
 __device__ __forceinline__ RayResult trace_ray(const TileK& T, const Ray<SPHERE>& r, unsigned& n_lb,
                                                unsigned& n_smp) {
   // no terrain rises above `top` (relative to h_p, at least 0)
-  const float top = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp : 0.0f;
+  const float t0 = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp : 0.0f;
+  const float top = r.dz > t0 ? r.dz : t0;
   if (MODE == SS_MODE_EXACT) return shadow_exact(T, r, top, n_lb, n_smp);
   if (MODE == SS_MODE_POINT) return shadow_dp<SPHERE, true>(T, r, top, n_lb, n_smp);
   if (MODE == SS_MODE_UNIFORM) return shadow_uniform(T, r, top, n_smp);

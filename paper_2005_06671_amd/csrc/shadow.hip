@@ -268,6 +268,53 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
   }
 }
 
+// Shadow rays from arbitrary surface points: point k at continuous texel
+// coordinates xy[k] (clamped to the tile), on the bilinear terrain there.
+template <bool SPHERE, int MODE>
+__global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __restrict__ xy,
+                                                     long long n, float* __restrict__ out) {
+  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const float2 q = xy[k];
+  const float qx = fminf(fmaxf(q.x, 0.0f), (float)T.W), qy = fminf(fmaxf(q.y, 0.0f), (float)T.H);
+  const int i = min((int)floorf(qx), T.W - 1), j = min((int)floorf(qy), T.H - 1);
+  // heights relative to the texel's own, the origin dz above it
+  const float ref = T.h[j * T.W + i];
+  Ray<SPHERE> r;
+  ray_init(T, i, j, ref, r, qx - ((float)i + 0.5f), qy - ((float)j + 0.5f),
+           terrain_above(T, qx, qy, ref));
+  unsigned n_lb = 0, n_smp = 0;
+  out[k] = disc_fraction(trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp).alpha, T);
+}
+
+template <bool SPHERE, int MODE>
+static void points_launch(const TileK& T, const float* xy, long long n, float* out,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL((points_kernel<SPHERE, MODE>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     stream, T, reinterpret_cast<const float2*>(xy), n, out);
+}
+
+template <bool SPHERE>
+static void points_mode(const TileK& T, int mode, const float* xy, long long n, float* out,
+                        hipStream_t stream) {
+  switch (mode) {
+    case SS_MODE_EXACT: points_launch<SPHERE, SS_MODE_EXACT>(T, xy, n, out, stream); break;
+    case SS_MODE_POINT: points_launch<SPHERE, SS_MODE_POINT>(T, xy, n, out, stream); break;
+    case SS_MODE_UNIFORM: points_launch<SPHERE, SS_MODE_UNIFORM>(T, xy, n, out, stream); break;
+    default: points_launch<SPHERE, SS_MODE_DP>(T, xy, n, out, stream); break;
+  }
+}
+
+hipError_t launch_points(const TileK& T, bool sphere, int mode, const float* xy, long long n,
+                         float* out, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (sphere)
+    points_mode<true>(T, mode, xy, n, out, stream);
+  else
+    points_mode<false>(T, mode, xy, n, out, stream);
+  return hipGetLastError();
+}
+
 static int tile_width_of(int code) {
   switch (code) {
     case SS_TILE_16x4: return 16;
