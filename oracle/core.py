@@ -14,7 +14,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "alternatives.c")]
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "alternatives.c"),
+        os.path.join(_HERE, "view.c")]
+_HDR = [os.path.join(_HERE, "oracle.h"), os.path.join(_HERE, "oracle_internal.h")]
 _lock = threading.RLock()
 _lib = None
 
@@ -45,12 +47,32 @@ TRACE_DTYPE = np.dtype([("seg", np.int32), ("n", np.int32), ("t", np.float64),
                         ("margin_tap", np.float64)], align=True)
 
 
+class _Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("eye", C.c_double * 3),
+                ("fwd", C.c_double * 3), ("right", C.c_double * 3), ("up", C.c_double * 3),
+                ("step_m", C.c_double), ("far_m", C.c_double)]
+
+
+class _ViewTol(C.Structure):
+    _fields_ = [("eh_abs", C.c_double), ("eh_rel", C.c_double), ("ep_abs", C.c_double),
+                ("ep_rel", C.c_double), ("max_samples", C.c_int64)]
+
+
+VIEW_MAXADM = 8
+VIEW_DTYPE = np.dtype([("n_hit", np.int32), ("n_adm", np.int32), ("adm", np.int32, VIEW_MAXADM),
+                       ("adm_overflow", np.int32), ("status", np.int32), ("t_hit", np.float64),
+                       ("qx", np.float64), ("qy", np.float64), ("f_prev", np.float64),
+                       ("f_hit", np.float64), ("eps", np.float64), ("dqdt", np.float64)],
+                      align=True)
+
+
 def load():
     global _lib
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_SO) or any(os.path.getmtime(s) > os.path.getmtime(_SO) for s in _SRC):
+        if not os.path.exists(_SO) or any(
+                os.path.getmtime(s) > os.path.getmtime(_SO) for s in _SRC + _HDR):
             build()
         lib = C.CDLL(_SO)
         P = C.POINTER
@@ -88,6 +110,14 @@ def load():
         lib.or_path_cells.argtypes = [C.c_void_p, P(_Params), C.c_int32, C.c_int32, C.c_int32,
                                       C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_int32]
         lib.or_path_cells.restype = C.c_int32
+        lib.or_view.argtypes = [C.c_void_p, C.c_double, C.c_double, P(_Camera), C.c_void_p,
+                                C.c_int64, P(_ViewTol), C.c_void_p]
+        lib.or_view.restype = C.c_int32
+        lib.or_view_direction.argtypes = [P(_Camera), C.c_int32, C.c_int32, C.c_void_p]
+        lib.or_view_direction.restype = None
+        lib.or_view_probe.argtypes = [C.c_void_p, C.c_double, C.c_double, P(_Camera), C.c_int32,
+                                      C.c_int32, C.c_double, C.c_void_p]
+        lib.or_view_probe.restype = None
         _lib = lib
         return lib
 
@@ -342,3 +372,90 @@ def path_cells(h: np.ndarray, p: Params, i: int, j: int, level: int, ta: float, 
                              cells.ctypes.data, ts.ctypes.data, 32)
     return [((int(cells[2 * k]), int(cells[2 * k + 1])), (float(ts[2 * k]), float(ts[2 * k + 1])))
             for k in range(n)]
+
+
+@dataclass
+class Camera:
+    """Pinhole camera in the tile frame (metres; eye relative to the point where the
+    tile's z axis meets the reference surface).  Pixel (px, py) looks along
+    fwd + sx*right + sy*up, sx = 2(px+1/2)/width - 1, sy = 1 - 2(py+1/2)/height."""
+    width: int
+    height: int
+    eye: tuple
+    fwd: tuple
+    right: tuple
+    up: tuple
+    step_m: float
+    far_m: float = 0.0
+
+    def c(self) -> _Camera:
+        v3 = C.c_double * 3
+        return _Camera(self.width, self.height, v3(*self.eye), v3(*self.fwd), v3(*self.right),
+                       v3(*self.up), self.step_m, self.far_m)
+
+
+@dataclass
+class ViewTol:
+    """Decision margins of the view oracle: heights eh_abs + eh_rel*(|eye|+t) plus the local
+    slope times the position tolerance ep_abs + ep_rel*(|eye|+t) (metres)."""
+    eh_abs: float = 0.0
+    eh_rel: float = 0.0
+    ep_abs: float = 0.0
+    ep_rel: float = 0.0
+    max_samples: int = 10_000_000
+
+    def c(self) -> _ViewTol:
+        return _ViewTol(self.eh_abs, self.eh_rel, self.ep_abs, self.ep_rel, self.max_samples)
+
+
+def view(h: np.ndarray, radius_m: float, texel_m: float, cam: Camera, pixels=None,
+         tol: ViewTol | None = None) -> np.ndarray:
+    """First hits of view rays (VIEW_DTYPE per pixel; [height, width] without pixels)."""
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    ctx = _ctx(h)
+    tol = tol or ViewTol()
+    if pixels is None:
+        n = cam.width * cam.height
+        pp = None
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        n = pixels.shape[0]
+        pp = pixels.ctypes.data
+    out = np.zeros(n, dtype=VIEW_DTYPE)
+    cc, tc = cam.c(), tol.c()
+    rc = load().or_view(ctx.ptr, float(radius_m), float(texel_m), C.byref(cc), pp, n,
+                        C.byref(tc), out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the view ({rc})")
+    return out.reshape(cam.height, cam.width) if pixels is None else out
+
+
+def view_threaded(h: np.ndarray, radius_m: float, texel_m: float, cam: Camera,
+                  tol: ViewTol | None = None, threads: int | None = None) -> np.ndarray:
+    """``view`` over all pixels, in row chunks on a thread pool."""
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    _ctx(h)
+    threads = threads or max(1, len(os.sched_getaffinity(0)))
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    pix = np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32)
+    chunks = np.array_split(pix, max(1, threads * 4))
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda q: view(h, radius_m, texel_m, cam, q, tol), chunks))
+    return np.concatenate(parts).reshape(cam.height, cam.width)
+
+
+def view_direction(cam: Camera, px: int, py: int) -> np.ndarray:
+    out = np.zeros(3, dtype=np.float64)
+    cc = cam.c()
+    load().or_view_direction(C.byref(cc), int(px), int(py), out.ctypes.data)
+    return out
+
+
+def view_probe(h: np.ndarray, radius_m: float, texel_m: float, cam: Camera, px: int, py: int,
+               t: float) -> dict:
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    out = np.zeros(6, dtype=np.float64)
+    cc = cam.c()
+    load().or_view_probe(_ctx(h).ptr, float(radius_m), float(texel_m), C.byref(cc), int(px),
+                         int(py), float(t), out.ctypes.data)
+    return dict(zip(["qx", "qy", "H", "terrain", "f", "defined"], out.tolist()))

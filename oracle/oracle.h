@@ -91,6 +91,45 @@ int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray,
                         double eh_abs, double eh_rel, double et_abs, double et_rel,
                         double* alpha_out, int32_t max_out);
 
+/* ---- view rays (Sec. 4, view ray casting); definitions in view.c ---- */
+typedef struct {
+  int32_t width, height;    /* image, pixels */
+  double eye[3];            /* tile frame, metres, relative to the point where the
+                               tile's z axis meets the reference surface */
+  double fwd[3], right[3], up[3]; /* pixel ray: fwd + sx right + sy up (normalised) */
+  double step_m;            /* sample spacing along the view ray */
+  double far_m;             /* samples beyond this ray length do not count; <= 0: none */
+} or_camera;
+
+typedef struct {
+  double eh_abs, eh_rel;    /* height tolerance eh_abs + eh_rel (|eye| + t), metres */
+  double ep_abs, ep_rel;    /* position tolerance ep_abs + ep_rel (|eye| + t), metres */
+  int64_t max_samples;      /* safety cap per ray (status -1 when exceeded) */
+} or_view_tol;
+
+#define OR_VIEW_MAXADM 8
+typedef struct {
+  int32_t n_hit;            /* first certain hit sample, -1: none (a miss is admissible) */
+  int32_t n_adm;            /* admissible first-hit samples (may exceed OR_VIEW_MAXADM) */
+  int32_t adm[OR_VIEW_MAXADM];
+  int32_t adm_overflow;
+  int32_t status;
+  double t_hit;             /* refined hit (INFINITY: none) */
+  double qx, qy;            /* texel coordinates at t_hit (NaN: none) */
+  double f_prev, f_hit;     /* f at t_{n-1} and t_n */
+  double eps;               /* height tolerance at the hit sample */
+  double dqdt;              /* |dq/dt| at t_hit, texels per metre */
+} or_view_hit;
+
+/* pixels: n (px, py) pairs, or NULL for all width*height pixels row by row.
+ * Returns 0, -1 for bad arguments, -2 for a pixel outside the image. */
+int32_t or_view(const or_ctx* c, double radius_m, double texel_m, const or_camera* cam,
+                const int32_t* pixels, int64_t n, const or_view_tol* tol, or_view_hit* out);
+void or_view_direction(const or_camera* cam, int32_t px, int32_t py, double* V);
+/* out6: qx, qy, H, terrain, f = H - terrain, defined (P_z > 0) */
+void or_view_probe(const or_ctx* c, double radius_m, double texel_m, const or_camera* cam,
+                   int32_t px, int32_t py, double t, double* out6);
+
 /* Inspection helpers used by the pins. */
 double or_disc_fraction(double d);
 int32_t or_schedule(const or_params* p, int32_t* m0_out, double* tau_out, double* delta_out);
