@@ -169,12 +169,52 @@ int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun, const ss
                                 const float* d_grad_shadow, float* d_grad_height,
                                 double* d_grad_sun, void* stream);
 
+/* ---- view rays (Sec. 4, view ray casting) -------------------------------- */
+
+#define SS_VIEW_HIER 0   /* skip empty space over the tap-bound pyramid */
+#define SS_VIEW_DENSE 1  /* test every grid sample between the clip points */
+
+/* Pinhole camera in the tile frame (metres).  The eye is given relative to the
+ * point where the tile's z axis meets the reference surface (the sphere centre
+ * is at (0, 0, -body_radius_m); on the plane, the tile centre at height 0).
+ * Pixel (px, py), row py from the top, looks along fwd + sx right + sy up,
+ * normalised, with sx = 2 (px + 1/2) / width - 1, sy = 1 - 2 (py + 1/2) /
+ * height; a pixel whose vector is zero sees nothing.  All values are rounded
+ * to float32 for the kernels. */
+typedef struct {
+  int32_t width, height;    /* image, 1..16384 each */
+  double eye_m[3];          /* |eye| < body_radius_m / 4 on the sphere */
+  double fwd[3], right[3], up[3];  /* finite; fwd nonzero */
+  double step_m;            /* sample spacing along the view ray, >= texel_m / 64 */
+  double far_m;             /* samples beyond this ray length do not count; <= 0: none */
+  int32_t mode;             /* SS_VIEW_* (results identical; the cost differs) */
+} ss_camera;
+
+/* First hit of every pixel's view ray with the bilinear terrain (Sec. 4: the
+ * view ray meets the same height field the shadow rays see; the shadow ray
+ * then starts there).  The ray eye + t V is sampled at t_n = n * step_m; a
+ * sample counts when its texel coordinates lie in the tile and t_n <= far_m;
+ * the hit is the first counting sample with H - b <= 0 (H the height above the
+ * reference surface, b the bilinear terrain over texel centres, taps clamped
+ * to the tile), refined by the zero of the line through (t_{n-1}, f_{n-1}) and
+ * (t_n, f_n) (t_{n-1} itself when f_{n-1} <= 0; 0 for n = 0).
+ * SS_VIEW_HIER starts where the terrain can be, as the paper's pre-displaced
+ * mesh does: it skips every tap-bound pyramid cell the ray passes above.
+ * Writes d_t[py][px] (ray length of the hit, +inf for none) and d_xy[py][px]
+ * (float2 texel coordinates of the hit, NaN for none; the input format of
+ * ss_shadow_points); d_steps, if not NULL, gets int32 pairs (grid samples
+ * tested, pyramid cells visited; the count is negated in the second entry if
+ * a ray hit its iteration bound, which valid input never does).  tile->bound
+ * (ss_bound_build) is required; tile->maxmip and the ray window are unused. */
+int32_t ss_view_cast(const ss_tile* tile, double body_radius_m, const ss_camera* cam,
+                     float* d_t, float* d_xy, int32_t* d_steps, void* stream);
+
 /* Shadow factor at n arbitrary surface points: d_xy holds n (x, y) float pairs
  * in continuous texel coordinates (texel i covers [i, i+1); 8-byte aligned),
  * each ray starts on the bilinear terrain there (Sec. 3.4's sampling) and runs
  * the chosen mode exactly as a texel-centre ray does; d_shadow[n] receives s.
- * Points outside the tile are clamped to its edge.  The ray window is
- * ignored.  Texel centres (i + 1/2, j + 1/2) give ss_shadow_cast's values.
+ * Points outside the tile are clamped to its edge; a point with a NaN
+ * coordinate (a view ray's miss) gets s = NaN.  The ray window is ignored.  Texel centres (i + 1/2, j + 1/2) give ss_shadow_cast's values.
  * This is the call a view-ray caster feeds (Sec. 4: shadows at the visible
  * surface points of a frame). */
 int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun, const ss_params* params,

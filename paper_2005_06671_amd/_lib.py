@@ -20,6 +20,8 @@ SS_MODE_POINT = 3
 SS_SCHED_GEOMETRIC = 0
 SS_SCHED_EQUAL = 1
 SS_SCHED_LIST = 2
+SS_VIEW_HIER = 0
+SS_VIEW_DENSE = 1
 RAY_TILES = {"8x8": 1, "16x4": 2, "4x16": 3, "32x2": 4}
 
 
@@ -39,6 +41,12 @@ class SSTile(C.Structure):
                 ("rows", C.c_int32), ("texel_m", C.c_double), ("bound", C.c_void_p),
                 ("ray_x0", C.c_int32), ("ray_y0", C.c_int32), ("ray_w", C.c_int32),
                 ("ray_h", C.c_int32)]
+
+
+class SSCamera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("eye_m", C.c_double * 3),
+                ("fwd", C.c_double * 3), ("right", C.c_double * 3), ("up", C.c_double * 3),
+                ("step_m", C.c_double), ("far_m", C.c_double), ("mode", C.c_int32)]
 
 
 # Every exported symbol with (restype, argtypes); the CPU tests check that this
@@ -78,6 +86,8 @@ SIGNATURES = {
     "ss_batched_plan_destroy": (C.c_int32, [C.c_void_p]),
     "ss_shadow_points": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_view_cast": (C.c_int32, [C.POINTER(SSTile), C.c_double, C.POINTER(SSCamera), C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
     "ss_probe_gather": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
                                     C.c_int64, C.c_void_p]),
     "ss_status_string": (C.c_char_p, [C.c_int32]),

@@ -292,6 +292,76 @@ def shadow_points(h: torch.Tensor, texel_m: float, elev: float, azim: float, xy:
     return out
 
 
+@dataclass
+class Camera:
+    """Pinhole camera in the tile frame (ss_camera): metres; the eye relative to the
+    point where the tile's z axis meets the reference surface.  Pixel (px, py)
+    looks along fwd + sx*right + sy*up, sx = 2(px+1/2)/width - 1,
+    sy = 1 - 2(py+1/2)/height."""
+    width: int
+    height: int
+    eye: tuple
+    fwd: tuple
+    right: tuple
+    up: tuple
+    step_m: float
+    far_m: float = 0.0
+    mode: int = L.SS_VIEW_HIER
+
+    def c(self) -> L.SSCamera:
+        v3 = C.c_double * 3
+        return L.SSCamera(int(self.width), int(self.height), v3(*map(float, self.eye)),
+                          v3(*map(float, self.fwd)), v3(*map(float, self.right)),
+                          v3(*map(float, self.up)), float(self.step_m), float(self.far_m),
+                          int(self.mode))
+
+
+def view_cast(h: torch.Tensor, texel_m: float, cam: Camera, radius_m: float = 1737400.0,
+              bound: torch.Tensor | None = None, steps: bool = False, out_t=None, out_xy=None):
+    """First hits of the camera's view rays (ss_view_cast).
+
+    Returns (t [H, W] float32, xy [H, W, 2] float32) and, with steps=True, the
+    int32 [H, W, 2] counts (grid samples tested, pyramid cells visited)."""
+    _dev_f32_2d(h)
+    if bound is None:
+        bound = bound_build(h)
+    shape = (int(cam.height), int(cam.width))
+    if out_t is None:
+        out_t = torch.empty(shape, dtype=torch.float32, device=h.device)
+    if out_xy is None:
+        out_xy = torch.empty(shape + (2,), dtype=torch.float32, device=h.device)
+    for t, sh, name in ((out_t, shape, "out_t"), (out_xy, shape + (2,), "out_xy")):
+        if (tuple(t.shape) != sh or t.dtype != torch.float32 or not t.is_contiguous()
+                or t.device != h.device):
+            raise ValueError(f"{name} must be a contiguous float32 tensor of shape {sh}")
+    st = torch.empty(shape + (2,), dtype=torch.int32, device=h.device) if steps else None
+    rows, width = h.shape
+    tile = L.SSTile(h.data_ptr(), None, width, rows, float(texel_m), bound.data_ptr(), 0, 0, 0, 0)
+    cc = cam.c()
+    L.check("ss_view_cast",
+            L.lib().ss_view_cast(C.byref(tile), float(radius_m), C.byref(cc), out_t.data_ptr(),
+                                 out_xy.data_ptr(), st.data_ptr() if steps else None,
+                                 _stream(h.device)))
+    return (out_t, out_xy, st) if steps else (out_t, out_xy)
+
+
+def frame(h: torch.Tensor, texel_m: float, cam: Camera, elev: float, azim: float,
+          ang_radius: float = SUN_RADIUS_RAD, params: Params | None = None,
+          mm: torch.Tensor | None = None, bound: torch.Tensor | None = None):
+    """One frame as Sec. 4 and 6.3 run it: view rays to the terrain, then a shadow ray
+    from every visible point.  Returns (s [H, W], t [H, W], xy [H, W, 2]); pixels that
+    see no terrain have s = NaN, t = +inf."""
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    if bound is None:
+        bound = bound_build(h)
+    t, xy = view_cast(h, texel_m, cam, params.radius_m, bound)
+    s = shadow_points(h, texel_m, elev, azim, xy.view(-1, 2), ang_radius, params, mm,
+                      bound=bound)
+    return s.view(t.shape), t, xy
+
+
 def probe_gather(src: torch.Tensor, window: int = 0, iters: int = 64, n_threads: int = 1 << 21,
                  out: torch.Tensor | None = None) -> torch.Tensor:
     """Memory-system gather probe (ss_probe_gather); returns the per-lane sums."""

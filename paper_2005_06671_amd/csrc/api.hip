@@ -353,6 +353,88 @@ extern "C" int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun,
   return SS_OK;
 }
 
+static bool finite3(const double* v) {
+  return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]);
+}
+
+extern "C" int32_t ss_view_cast(const ss_tile* tile, double body_radius_m, const ss_camera* cam,
+                                float* d_t, float* d_xy, int32_t* d_steps, void* stream) {
+  if (!tile || !cam) return SS_ERR_INVALID_ARG;
+  // heights and the bound pyramid are read; the max-mip and the ray window are not
+  if (!size_ok(tile->width, tile->rows) || !tile->height || !tile->bound) return SS_ERR_INVALID_ARG;
+  if (!(tile->texel_m > 0.0) || isinf(tile->texel_m)) return SS_ERR_INVALID_ARG;
+  if (!(body_radius_m > 0.0)) return SS_ERR_INVALID_ARG;
+  const bool sphere = !isinf(body_radius_m);
+  if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
+    return SS_ERR_INVALID_ARG;
+  if (!finite3(cam->eye_m) || !finite3(cam->fwd) || !finite3(cam->right) || !finite3(cam->up))
+    return SS_ERR_INVALID_ARG;
+  if (cam->fwd[0] == 0.0 && cam->fwd[1] == 0.0 && cam->fwd[2] == 0.0) return SS_ERR_INVALID_ARG;
+  const double eyen = sqrt(cam->eye_m[0] * cam->eye_m[0] + cam->eye_m[1] * cam->eye_m[1] +
+                           cam->eye_m[2] * cam->eye_m[2]);
+  if (sphere && !(eyen < 0.25 * body_radius_m)) return SS_ERR_INVALID_ARG;
+  if (!(cam->step_m >= tile->texel_m / 64.0) || !isfinite(cam->step_m)) return SS_ERR_INVALID_ARG;
+  if (!(cam->far_m <= 0.0) && !(cam->far_m > 0.0 && isfinite(cam->far_m)))
+    return SS_ERR_INVALID_ARG;
+  if (cam->mode != SS_VIEW_HIER && cam->mode != SS_VIEW_DENSE) return SS_ERR_INVALID_ARG;
+  if (!d_t || !d_xy) return SS_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(d_xy) & 7) != 0 ||
+      (reinterpret_cast<uintptr_t>(d_steps) & 7) != 0)
+    return SS_ERR_INVALID_ARG;
+  const int W = tile->width, H = tile->rows, L = levels_of(W, H);
+  if (L > SS_MAXLEV) return SS_ERR_UNSUPPORTED;
+  ViewK K;
+  memset(&K, 0, sizeof(K));
+  K.h = tile->height;
+  K.bnd = tile->bound;
+  K.bmm = tile->bound + bound_base(W, H);
+  K.W = W;
+  K.H = H;
+  K.L = L;
+  for (int m = 0; m < L; ++m) {
+    dims_of(W, H, m, &K.lw[m], &K.lh[m]);
+    K.loff[m] = m == 0 ? 0 : (int)ss_maxmip_level_offset(W, H, m);
+    K.inv_pow2[m] = (float)ldexp(1.0, -m);
+  }
+  K.texel = (float)tile->texel_m;
+  K.invT = (float)(1.0 / tile->texel_m);
+  K.R = sphere ? (float)body_radius_m : 0.0f;
+  K.invR = sphere ? (float)(1.0 / body_radius_m) : 0.0f;
+  K.cx0 = (float)(0.5 * W);
+  K.cy0 = (float)(0.5 * H);
+  K.ex = (float)cam->eye_m[0];
+  K.ey = (float)cam->eye_m[1];
+  K.ez = (float)cam->eye_m[2];
+  K.fx = (float)cam->fwd[0];
+  K.fy = (float)cam->fwd[1];
+  K.fz = (float)cam->fwd[2];
+  K.rx = (float)cam->right[0];
+  K.ry = (float)cam->right[1];
+  K.rz = (float)cam->right[2];
+  K.ux = (float)cam->up[0];
+  K.uy = (float)cam->up[1];
+  K.uz = (float)cam->up[2];
+  K.img_w = cam->width;
+  K.img_h = cam->height;
+  K.nbx = (cam->width + 15) / 16;
+  K.nby = (cam->height + 15) / 16;
+  K.inv_w2 = (float)(2.0 / cam->width);
+  K.inv_h2 = (float)(2.0 / cam->height);
+  K.step = (float)cam->step_m;
+  K.inv_step = (float)(1.0 / (double)K.step);
+  K.far = cam->far_m > 0.0 ? (float)cam->far_m : INFINITY;
+  // The skip test compares the ray's lowest FP32 height over a cell with the
+  // cell's bound; the margin covers FP32 rounding of heights (absolute
+  // heights of a few km: a few ulps of 1e-3 m), of the ray point (relative
+  // 1e-7 of |eye| + t) and of the sample positions against the cell limits.
+  K.m_abs = 1e-2f;
+  K.m_rel = 2e-6f;
+  K.max_iter = 4 * (W + H + 8) * (L + 2) + 64;
+  K.max_samples = 1 << 26;
+  SS_HIP(launch_view(K, sphere, cam->mode, d_t, d_xy, d_steps, (hipStream_t)stream));
+  return SS_OK;
+}
+
 extern "C" int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t window,
                                    int32_t iters, float* d_out, int64_t n_threads, void* stream) {
   if (!d_src || !d_out || n_floats < 1 || n_floats > (1LL << 32) || iters < 1) return SS_ERR_INVALID_ARG;

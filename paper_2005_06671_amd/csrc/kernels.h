@@ -42,6 +42,30 @@ hipError_t launch_batched(const TileK* d_pairs, float* const* d_out_ptrs, const 
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream);
 int batched_workgroups(bool sphere, int mode, int ray_tile);
 
+// View rays (pinhole camera) onto the terrain; the host fills every field.
+struct ViewK {
+  const float* h;            // heightfield [H][W]
+  const float* bnd;          // tap-bound pyramid level 0, [H][W]
+  const float* bmm;          // its levels >= 1 at loff[m]
+  int W, H, L;
+  int lw[SS_MAXLEV], lh[SS_MAXLEV], loff[SS_MAXLEV];
+  float inv_pow2[SS_MAXLEV]; // 2^-m
+  float texel, invT;         // texel spacing and its inverse
+  float R, invR;             // body radius and its inverse (0 on the plane)
+  float cx0, cy0;            // W/2, H/2: texel coordinates of the tile centre
+  float ex, ey, ez;          // eye, relative to the tile-centre surface point
+  float fx, fy, fz, rx, ry, rz, ux, uy, uz;  // pixel ray: f + sx r + sy u
+  int img_w, img_h, nbx, nby;
+  float inv_w2, inv_h2;      // 2 / img_w, 2 / img_h
+  float step, inv_step;      // grid spacing along the ray (m) and its inverse
+  float far;                 // last counting ray length (+inf: none)
+  float m_abs, m_rel;        // skip margin m_abs + m_rel (|eye| + t), metres
+  int max_iter;              // walk iterations per ray (a bound never reached)
+  int max_samples;           // samples per ray (a bound never reached)
+};
+hipError_t launch_view(const ViewK& K, bool sphere, int mode, float* t, float* xy, int* steps,
+                       hipStream_t stream);
+
 // Gather throughput probe (measurement only).
 hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
                                float* out, long long n_threads, hipStream_t stream);

@@ -276,6 +276,10 @@ __global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __re
   const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
   const float2 q = xy[k];
+  if (q.x != q.x || q.y != q.y) {  // a view ray's miss: nothing to shade
+    out[k] = NAN;
+    return;
+  }
   const float qx = fminf(fmaxf(q.x, 0.0f), (float)T.W), qy = fminf(fmaxf(q.y, 0.0f), (float)T.H);
   const int i = min((int)floorf(qx), T.W - 1), j = min((int)floorf(qy), T.H - 1);
   // heights relative to the texel's own, the origin dz above it

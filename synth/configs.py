@@ -77,3 +77,56 @@ def dem_for(name: str, tile: int = 0, device="cpu"):
     w, r, texel = c["tiles"][tile]
     return make_dem(w, r, texel, c["amplitude"], seed_of(name, tile), craters=c["craters"],
                     device=device)
+
+
+def look_at(eye, target, hfov_deg: float, width: int, height: int, step_m: float,
+            far_m: float = 0.0) -> dict:
+    """Pinhole camera fields (eye, fwd, right, up, ...) looking from eye to target, both in
+    the tile frame relative to the tile-centre surface point; square pixels."""
+    import numpy as np
+    e = np.asarray(eye, dtype=np.float64)
+    f = np.asarray(target, dtype=np.float64) - e
+    f /= np.linalg.norm(f)
+    z = np.array([0.0, 0.0, 1.0]) if abs(f[2]) < 0.999 else np.array([0.0, 1.0, 0.0])
+    r = np.cross(f, z)
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    th = math.tan(math.radians(hfov_deg) / 2.0)
+    tv = th * height / width
+    return dict(width=int(width), height=int(height), eye=tuple(e.tolist()),
+                fwd=tuple(f.tolist()), right=tuple((th * r).tolist()), up=tuple((tv * u).tolist()),
+                step_m=float(step_m), far_m=float(far_m))
+
+
+def view_scene(kind: str, width_px: int, height_px: int, tile_w: int, tile_h: int,
+               texel_m: float, step_m: float | None = None) -> dict:
+    """Camera recipes over a tile of tile_w x tile_h texels (side S = tile_w * texel_m):
+    oblique   -- 0.35 S back from a corner, 0.5 S up, looking at the tile centre;
+    grazing   -- low over one edge, looking across the tile toward the horizon (sky,
+                 long rays, far misses);
+    nadir     -- 0.4 S above the centre looking straight down (rays along the local
+                 vertical, where the texture path barely moves);
+    outside   -- beyond the tile's -x edge at 400 m, looking inward (side entries);
+    flyover   -- the frame workload: 8 km up over the tile's south-west quarter,
+                 heading north-east, 25 degrees below the horizon, 60 degree field of view
+                 (a spacecraft passing over mountains)."""
+    S = tile_w * texel_m
+    step = step_m if step_m is not None else 0.5 * texel_m
+    if kind == "oblique":
+        return look_at((-0.35 * S, -0.3 * S, 0.5 * S), (0.0, 0.0, 0.0), 60.0, width_px,
+                       height_px, step)
+    if kind == "grazing":
+        return look_at((-0.45 * S, 0.05 * S, 2600.0), (0.5 * S, 0.1 * S, 1800.0), 70.0,
+                       width_px, height_px, step)
+    if kind == "nadir":
+        return look_at((0.02 * S, -0.01 * S, 0.4 * S), (0.02 * S, -0.01 * S, 0.0), 40.0,
+                       width_px, height_px, step)
+    if kind == "outside":
+        return look_at((-0.6 * S, 0.1 * S, 400.0), (0.2 * S, 0.0, -300.0), 60.0, width_px,
+                       height_px, step)
+    if kind == "flyover":
+        eye = (-0.3 * S, -0.3 * S, 8000.0)
+        d = 8000.0 / math.tan(math.radians(25.0))
+        tgt = (eye[0] + d / math.sqrt(2.0), eye[1] + d / math.sqrt(2.0), 0.0)
+        return look_at(eye, tgt, 60.0, width_px, height_px, step)
+    raise KeyError(kind)

@@ -209,3 +209,40 @@ def test_product_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libsoftshadow.so")
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_view_validation(L):
+    """ss_view_cast checks the tile, the camera and the buffers before any launch."""
+    lib = L.lib()
+    fake = 0x100000
+    v3 = C.c_double * 3
+
+    def cam(**kw):
+        c = L.SSCamera(64, 32, v3(0.0, 0.0, 500.0), v3(0.0, 1.0, -0.5), v3(0.5, 0.0, 0.0),
+                       v3(0.0, 0.2, 0.4), 5.0, 0.0, L.SS_VIEW_HIER)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return c
+
+    def call(t=None, radius=1737400.0, c=None, out_t=fake, out_xy=fake, steps=None):
+        t = t or L.SSTile(fake, fake, 64, 64, 10.0, fake, 0, 0, 0, 0)
+        c = c or cam()
+        return lib.ss_view_cast(C.byref(t), radius, C.byref(c), out_t, out_xy, steps, None)
+
+    assert call(t=L.SSTile(fake, fake, 64, 64, 10.0, None, 0, 0, 0, 0)) == L.SS_ERR_INVALID_ARG
+    assert call(t=L.SSTile(fake, fake, 0, 64, 10.0, fake, 0, 0, 0, 0)) == L.SS_ERR_INVALID_ARG
+    assert call(t=L.SSTile(None, fake, 64, 64, 10.0, fake, 0, 0, 0, 0)) == L.SS_ERR_INVALID_ARG
+    assert call(t=L.SSTile(fake, fake, 64, 64, 0.0, fake, 0, 0, 0, 0)) == L.SS_ERR_INVALID_ARG
+    assert call(radius=0.0) == L.SS_ERR_INVALID_ARG
+    assert call(radius=-math.inf) == L.SS_ERR_INVALID_ARG
+    for bad in [dict(width=0), dict(height=-1), dict(width=16385), dict(step_m=0.1),
+                dict(step_m=math.nan), dict(far_m=math.nan), dict(far_m=math.inf), dict(mode=2),
+                dict(fwd=v3(0.0, 0.0, 0.0)), dict(right=v3(math.nan, 0.0, 0.0)),
+                dict(eye_m=v3(0.0, 0.0, 1737400.0 / 4))]:
+        assert call(c=cam(**bad)) == L.SS_ERR_INVALID_ARG, bad
+    # the eye limit applies on the sphere only
+    assert call(radius=math.inf, c=cam(eye_m=v3(0.0, 0.0, 1e6)), out_t=None) == L.SS_ERR_INVALID_ARG
+    assert call(out_t=None) == L.SS_ERR_INVALID_ARG
+    assert call(out_xy=None) == L.SS_ERR_INVALID_ARG
+    assert call(out_xy=fake + 4) == L.SS_ERR_INVALID_ARG
+    assert call(steps=fake + 4) == L.SS_ERR_INVALID_ARG
