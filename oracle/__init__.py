@@ -4,7 +4,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
 leg may import this package.  It shares no code with the HIP library and never
 reads anything the GPU path produced.
 
-The numerics live in plain C (``oracle.c``, ``alternatives.c``, ``view.c``), compiled with
+The numerics live in plain C (``oracle.c``, ``alternatives.c``, ``view.c``, ``resample.c``), compiled with
 gcc into ``liboracle.so`` and called through ctypes; the reference gradient is
 torch float64 autograd (``grad_ref.py``).
 """
@@ -13,4 +13,5 @@ from .core import (  # noqa: F401
     alternatives,
     disc_fraction, schedule, ray_consts, probe, path_cells, tap_bound, TRACE_DTYPE,
     Camera, ViewTol, VIEW_DTYPE, view, view_threaded, view_direction, view_probe,
+    Frame, resample, frame_source_coords,
 )

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "alternatives.c"),
-        os.path.join(_HERE, "view.c")]
+        os.path.join(_HERE, "view.c"), os.path.join(_HERE, "resample.c")]
 _HDR = [os.path.join(_HERE, "oracle.h"), os.path.join(_HERE, "oracle_internal.h")]
 _lock = threading.RLock()
 _lib = None
@@ -56,6 +56,12 @@ class _Camera(C.Structure):
 class _ViewTol(C.Structure):
     _fields_ = [("eh_abs", C.c_double), ("eh_rel", C.c_double), ("ep_abs", C.c_double),
                 ("ep_rel", C.c_double), ("max_samples", C.c_int64)]
+
+
+class _Frame(C.Structure):
+    _fields_ = [("width", C.c_int32), ("rows", C.c_int32), ("texel_m", C.c_double),
+                ("centre", C.c_double * 3), ("ex", C.c_double * 3), ("ey", C.c_double * 3),
+                ("origin_m", C.c_double * 2)]
 
 
 VIEW_MAXADM = 8
@@ -118,6 +124,12 @@ def load():
         lib.or_view_probe.argtypes = [C.c_void_p, C.c_double, C.c_double, P(_Camera), C.c_int32,
                                       C.c_int32, C.c_double, C.c_void_p]
         lib.or_view_probe.restype = None
+        lib.or_resample.argtypes = [C.c_void_p, P(_Frame), P(_Frame), C.c_double, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.or_resample.restype = C.c_int32
+        lib.or_frame_source_coords.argtypes = [P(_Frame), P(_Frame), C.c_double, C.c_int32,
+                                               C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.or_frame_source_coords.restype = None
         _lib = lib
         return lib
 
@@ -459,3 +471,47 @@ def view_probe(h: np.ndarray, radius_m: float, texel_m: float, cam: Camera, px: 
     load().or_view_probe(_ctx(h).ptr, float(radius_m), float(texel_m), C.byref(cc), int(px),
                          int(py), float(t), out.ctypes.data)
     return dict(zip(["qx", "qy", "H", "terrain", "f", "defined"], out.tolist()))
+
+
+@dataclass
+class Frame:
+    """Gnomonic tile frame: plane tangent at unit vector ``centre`` with unit axes ex (+column)
+    and ey (+row), texel spacing texel_m in the plane, grid centre at plane coordinates
+    ``origin``."""
+    width: int
+    rows: int
+    texel_m: float
+    centre: tuple
+    ex: tuple
+    ey: tuple
+    origin: tuple = (0.0, 0.0)
+
+    def c(self) -> _Frame:
+        v3, v2 = C.c_double * 3, C.c_double * 2
+        return _Frame(self.width, self.rows, self.texel_m, v3(*self.centre), v3(*self.ex),
+                      v3(*self.ey), v2(*self.origin))
+
+
+def resample(src: np.ndarray, fs: Frame, fd: Frame, radius_m: float, dst=None):
+    """(dst float32, dst float64, covered bool, edge margin) of resampling src into fd."""
+    src = np.ascontiguousarray(src, dtype=np.float32)
+    assert src.shape == (fs.rows, fs.width)
+    out = (np.full((fd.rows, fd.width), np.nan, dtype=np.float32) if dst is None
+           else np.ascontiguousarray(dst, dtype=np.float32).copy())
+    o64 = np.full((fd.rows, fd.width), np.nan)
+    cov = np.zeros((fd.rows, fd.width), dtype=np.uint8)
+    mar = np.zeros((fd.rows, fd.width))
+    a, b = fs.c(), fd.c()
+    rc = load().or_resample(src.ctypes.data, C.byref(a), C.byref(b), float(radius_m),
+                            out.ctypes.data, o64.ctypes.data, cov.ctypes.data, mar.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the frames")
+    return out, o64, cov.astype(bool), mar
+
+
+def frame_source_coords(fs: Frame, fd: Frame, radius_m: float, i: int, j: int):
+    qx, qy, fr = C.c_double(), C.c_double(), C.c_double()
+    a, b = fs.c(), fd.c()
+    load().or_frame_source_coords(C.byref(a), C.byref(b), float(radius_m), int(i), int(j),
+                                  C.byref(qx), C.byref(qy), C.byref(fr))
+    return qx.value, qy.value, fr.value

@@ -130,6 +130,23 @@ void or_view_direction(const or_camera* cam, int32_t px, int32_t py, double* V);
 void or_view_probe(const or_ctx* c, double radius_m, double texel_m, const or_camera* cam,
                    int32_t px, int32_t py, double t, double* out6);
 
+/* ---- tiles in different gnomonic frames (Sec. 3.3, Sec. 4); resample.c ---- */
+typedef struct {
+  int32_t width, rows;
+  double texel_m;
+  double centre[3];         /* unit tangent point, planet frame */
+  double ex[3], ey[3];      /* unit plane axes: +column, +row */
+  double origin_m[2];       /* plane coordinates of the grid centre */
+} or_frame;
+
+/* Destination texels whose direction projects into the source tile get the
+ * source's bilinear height (FP64, rounded once into dst); others are left
+ * alone.  Any of dst, dst64, covered, edge_margin may be NULL. */
+int32_t or_resample(const float* src, const or_frame* fs, const or_frame* fd, double radius_m,
+                    float* dst, double* dst64, uint8_t* covered, double* edge_margin);
+void or_frame_source_coords(const or_frame* fs, const or_frame* fd, double R, int i, int j,
+                            double* qx, double* qy, double* front);
+
 /* Inspection helpers used by the pins. */
 double or_disc_fraction(double d);
 int32_t or_schedule(const or_params* p, int32_t* m0_out, double* tau_out, double* delta_out);
