@@ -169,6 +169,38 @@ int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun, const ss
                                 const float* d_grad_shadow, float* d_grad_height,
                                 double* d_grad_sun, void* stream);
 
+/* ---- tiles in other gnomonic frames (Sec. 3.3 virtual texture, Sec. 4) ---- */
+
+/* A tile frame: the plane tangent to the reference sphere at the unit vector
+ * `centre` (planet frame), with unit axes ex (+column) and ey (+row)
+ * orthogonal to it and to each other (each within 1e-9), texel spacing
+ * texel_m in that plane and the plane coordinates origin_m of the grid centre.
+ * Texel (i, j) stands for the surface direction of R centre + X ex + Y ey,
+ * X = origin_m[0] + (i + 1/2 - width/2) texel_m (Y likewise).  A tile of this
+ * library (gnomonic about its own centre) has origin_m = (0, 0); a sub-tile of
+ * a cube face shares the face's centre and axes and has its own origin_m. */
+typedef struct {
+  int32_t width, rows;
+  double texel_m;
+  double centre[3];
+  double ex[3], ey[3];
+  double origin_m[2];
+} ss_frame;
+
+/* Resamples a source tile into a destination tile in another frame (Sec. 3.3:
+ * the visible tiles are stitched into one texture; Sec. 4: tiles lie on
+ * different cube faces).  Every destination texel whose direction projects
+ * centrally into the source tile [0, width) x [0, rows) (in front of its
+ * plane) receives the source's bilinear height there (texel centres, taps
+ * clamped to the tile, the shadow path's sampling rule); other texels are not
+ * written, so several sources composite in call order.  Heights are radial and
+ * carry over unchanged.  Positions and the blend are FP64 in a fixed order,
+ * rounded once to float32, so the result is a function of the definition
+ * alone.  d_src and d_dst must not overlap.  Build a core tile plus a halo
+ * from its neighbours this way, then shade the core with a ray window. */
+int32_t ss_resample(const float* d_src, const ss_frame* src, float* d_dst, const ss_frame* dst,
+                    double body_radius_m, void* stream);
+
 /* ---- view rays (Sec. 4, view ray casting) -------------------------------- */
 
 #define SS_VIEW_HIER 0   /* skip empty space over the tap-bound pyramid */

@@ -49,6 +49,12 @@ class SSCamera(C.Structure):
                 ("step_m", C.c_double), ("far_m", C.c_double), ("mode", C.c_int32)]
 
 
+class SSFrame(C.Structure):
+    _fields_ = [("width", C.c_int32), ("rows", C.c_int32), ("texel_m", C.c_double),
+                ("centre", C.c_double * 3), ("ex", C.c_double * 3), ("ey", C.c_double * 3),
+                ("origin_m", C.c_double * 2)]
+
+
 # Every exported symbol with (restype, argtypes); the CPU tests check that this
 # list matches include/softshadow.h.
 SIGNATURES = {
@@ -88,6 +94,8 @@ SIGNATURES = {
                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ss_view_cast": (C.c_int32, [C.POINTER(SSTile), C.c_double, C.POINTER(SSCamera), C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ss_resample": (C.c_int32, [C.c_void_p, C.POINTER(SSFrame), C.c_void_p, C.POINTER(SSFrame),
+                                C.c_double, C.c_void_p]),
     "ss_probe_gather": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
                                     C.c_int64, C.c_void_p]),
     "ss_status_string": (C.c_char_p, [C.c_int32]),

@@ -362,6 +362,51 @@ def frame(h: torch.Tensor, texel_m: float, cam: Camera, elev: float, azim: float
     return s.view(t.shape), t, xy
 
 
+@dataclass
+class Frame:
+    """Gnomonic tile frame (ss_frame): plane tangent at unit vector ``centre`` (planet frame),
+    unit axes ex (+column) and ey (+row), texel spacing texel_m in the plane, grid centre at
+    plane coordinates ``origin`` (metres)."""
+    width: int
+    rows: int
+    texel_m: float
+    centre: tuple
+    ex: tuple
+    ey: tuple
+    origin: tuple = (0.0, 0.0)
+
+    def c(self) -> L.SSFrame:
+        v3, v2 = C.c_double * 3, C.c_double * 2
+        return L.SSFrame(int(self.width), int(self.rows), float(self.texel_m),
+                         v3(*map(float, self.centre)), v3(*map(float, self.ex)),
+                         v3(*map(float, self.ey)), v2(*map(float, self.origin)))
+
+
+def resample(src: torch.Tensor, fs: Frame, dst: torch.Tensor, fd: Frame,
+             radius_m: float = 1737400.0) -> torch.Tensor:
+    """Writes src's heights into the texels of dst that fall inside src (ss_resample)."""
+    _dev_f32_2d(src, "src")
+    _dev_f32_2d(dst, "dst")
+    if tuple(src.shape) != (fs.rows, fs.width) or tuple(dst.shape) != (fd.rows, fd.width):
+        raise ValueError("tensor shapes must match their frames")
+    a, b = fs.c(), fd.c()
+    L.check("ss_resample", L.lib().ss_resample(src.data_ptr(), C.byref(a), dst.data_ptr(),
+                                               C.byref(b), float(radius_m), _stream(dst.device)))
+    return dst
+
+
+def stitch(sources, fd: Frame, radius_m: float = 1737400.0, out: torch.Tensor | None = None,
+           device=None) -> torch.Tensor:
+    """One tile in frame fd from (heights, Frame) sources, later sources over earlier ones;
+    texels no source covers stay NaN."""
+    if out is None:
+        dev = device if device is not None else sources[0][0].device
+        out = torch.full((fd.rows, fd.width), float("nan"), dtype=torch.float32, device=dev)
+    for h, f in sources:
+        resample(h, f, out, fd, radius_m)
+    return out
+
+
 def probe_gather(src: torch.Tensor, window: int = 0, iters: int = 64, n_threads: int = 1 << 21,
                  out: torch.Tensor | None = None) -> torch.Tensor:
     """Memory-system gather probe (ss_probe_gather); returns the per-lane sums."""

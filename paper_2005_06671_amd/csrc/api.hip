@@ -435,6 +435,58 @@ extern "C" int32_t ss_view_cast(const ss_tile* tile, double body_radius_m, const
   return SS_OK;
 }
 
+static bool frame_ok(const ss_frame* f) {
+  if (!f || !size_ok(f->width, f->rows)) return false;
+  if (!(f->texel_m > 0.0) || isinf(f->texel_m)) return false;
+  if (!finite3(f->centre) || !finite3(f->ex) || !finite3(f->ey)) return false;
+  if (!isfinite(f->origin_m[0]) || !isfinite(f->origin_m[1])) return false;
+  auto dot = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+  const double tol = 1e-9;
+  if (fabs(dot(f->centre, f->centre) - 1.0) > tol || fabs(dot(f->ex, f->ex) - 1.0) > tol ||
+      fabs(dot(f->ey, f->ey) - 1.0) > tol)
+    return false;
+  if (fabs(dot(f->centre, f->ex)) > tol || fabs(dot(f->centre, f->ey)) > tol ||
+      fabs(dot(f->ex, f->ey)) > tol)
+    return false;
+  return true;
+}
+
+extern "C" int32_t ss_resample(const float* d_src, const ss_frame* src, float* d_dst,
+                               const ss_frame* dst, double body_radius_m, void* stream) {
+  if (!d_src || !d_dst || !frame_ok(src) || !frame_ok(dst)) return SS_ERR_INVALID_ARG;
+  if (!(body_radius_m > 0.0) || isinf(body_radius_m)) return SS_ERR_INVALID_ARG;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(d_src);
+  const uintptr_t a1 = a0 + (uintptr_t)src->width * (uintptr_t)src->rows * 4u;
+  const uintptr_t b0 = reinterpret_cast<uintptr_t>(d_dst);
+  const uintptr_t b1 = b0 + (uintptr_t)dst->width * (uintptr_t)dst->rows * 4u;
+  if (a0 < b1 && b0 < a1) return SS_ERR_INVALID_ARG;
+  ResampleK K;
+  memset(&K, 0, sizeof(K));
+  K.src = d_src;
+  K.dst = d_dst;
+  K.Ws = src->width;
+  K.Hs = src->rows;
+  K.Wd = dst->width;
+  K.Hd = dst->rows;
+  K.R = body_radius_m;
+  for (int k = 0; k < 3; ++k) {
+    K.cd[k] = dst->centre[k];
+    K.exd[k] = dst->ex[k];
+    K.eyd[k] = dst->ey[k];
+    K.cs[k] = src->centre[k];
+    K.exs[k] = src->ex[k];
+    K.eys[k] = src->ey[k];
+  }
+  K.oxd = dst->origin_m[0];
+  K.oyd = dst->origin_m[1];
+  K.Dd = dst->texel_m;
+  K.oxs = src->origin_m[0];
+  K.oys = src->origin_m[1];
+  K.Ds = src->texel_m;
+  SS_HIP(launch_resample(K, (hipStream_t)stream));
+  return SS_OK;
+}
+
 extern "C" int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t window,
                                    int32_t iters, float* d_out, int64_t n_threads, void* stream) {
   if (!d_src || !d_out || n_floats < 1 || n_floats > (1LL << 32) || iters < 1) return SS_ERR_INVALID_ARG;

@@ -66,6 +66,17 @@ struct ViewK {
 hipError_t launch_view(const ViewK& K, bool sphere, int mode, float* t, float* xy, int* steps,
                        hipStream_t stream);
 
+// Resampling between gnomonic tile frames (FP64 definition, rounded once).
+struct ResampleK {
+  const float* src;
+  float* dst;
+  int Ws, Hs, Wd, Hd;
+  double R;
+  double cd[3], exd[3], eyd[3], oxd, oyd, Dd;  // destination frame
+  double cs[3], exs[3], eys[3], oxs, oys, Ds;  // source frame
+};
+hipError_t launch_resample(const ResampleK& K, hipStream_t stream);
+
 // Gather throughput probe (measurement only).
 hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
                                float* out, long long n_threads, hipStream_t stream);

@@ -246,3 +246,36 @@ def test_view_validation(L):
     assert call(out_xy=None) == L.SS_ERR_INVALID_ARG
     assert call(out_xy=fake + 4) == L.SS_ERR_INVALID_ARG
     assert call(steps=fake + 4) == L.SS_ERR_INVALID_ARG
+
+
+def test_resample_validation(L):
+    """ss_resample checks both frames (orthonormal, finite, sizes) and the buffers."""
+    lib = L.lib()
+    v3, v2 = C.c_double * 3, C.c_double * 2
+
+    def fr(**kw):
+        f = L.SSFrame(64, 32, 10.0, v3(0.0, 0.0, 1.0), v3(1.0, 0.0, 0.0), v3(0.0, 1.0, 0.0),
+                      v2(0.0, 0.0))
+        for k, v in kw.items():
+            setattr(f, k, v)
+        return f
+
+    src, dst = 0x100000, 0x800000
+
+    def call(fs=None, fd=None, s=src, d=dst, radius=1737400.0):
+        a, b = fs or fr(), fd or fr()
+        return lib.ss_resample(s, C.byref(a), d, C.byref(b), radius, None)
+
+    for bad in [dict(width=0), dict(rows=70000), dict(texel_m=0.0), dict(texel_m=math.inf),
+                dict(centre=v3(0.0, 0.0, 2.0)), dict(ex=v3(1.0, 0.0, 0.1)),
+                dict(ey=v3(1.0, 0.0, 0.0)), dict(centre=v3(math.nan, 0.0, 1.0)),
+                dict(origin_m=v2(math.inf, 0.0))]:
+        assert call(fs=fr(**bad)) == L.SS_ERR_INVALID_ARG, bad
+        assert call(fd=fr(**bad)) == L.SS_ERR_INVALID_ARG, bad
+    assert call(s=None) == L.SS_ERR_INVALID_ARG
+    assert call(d=None) == L.SS_ERR_INVALID_ARG
+    assert call(radius=0.0) == L.SS_ERR_INVALID_ARG
+    assert call(radius=math.inf) == L.SS_ERR_INVALID_ARG
+    # overlapping buffers (64 x 32 floats = 8 KiB)
+    assert call(d=src + 4096) == L.SS_ERR_INVALID_ARG
+    assert call(s=dst + 8188) == L.SS_ERR_INVALID_ARG
