@@ -476,6 +476,46 @@ def leg_frame(ss, reps=10):
     return out
 
 
+def leg_stitch(ss, reps=10):
+    """Building a working tile from tiles in other frames (Sec. 3.3 stitched virtual texture,
+    Sec. 4 cube faces): a 4096^2 tile at 5 m/texel tangent 1.2 km from the +z/+x face seam,
+    resampled from two 6144^2 cube-face sub-tiles meeting there (two launches), then its
+    2048^2 core shaded through a ray window (descent, 30 km cap, e = 1.5 deg from across the
+    seam).  Stitch rate in destination texels/s and in bytes/s against HBM, counting the
+    algorithmic 4 bytes written plus 4 read per destination texel (neighbouring texels share
+    their source taps)."""
+    import math
+    import torch
+    from synth import R_MOON
+    from synth.planet import seam_frames
+    fa, fb, fw = seam_frames(core=2048, halo=1024, texel_m=5.0, n_src=6144)
+    dev = "cuda"
+    gen = torch.Generator(device=dev).manual_seed(7)
+    srcs = [(torch.rand((f["rows"], f["width"]), generator=gen, device=dev) * 2000.0 - 500.0,
+             ss.Frame(**f)) for f in (fa, fb)]
+    W = fw["width"]
+    out = torch.empty((W, W), dtype=torch.float32, device=dev)
+    fr = ss.Frame(**fw)
+    ss.stitch(srcs, fr, R_MOON, out=out)
+    ts = _timed(lambda: ss.stitch(srcs, fr, R_MOON, out=out), reps)
+    ms = min(ts)
+    nan = int(torch.isnan(out).sum())
+    win = (1024, 1024, 2048, 2048)
+    p = ss.Params(radius_m=R_MOON, max_len_m=30000.0)
+    mm = ss.maxmip(out)
+    s = torch.empty((2048, 2048), dtype=torch.float32, device=dev)
+    e, a, r = math.radians(1.5), 0.0, math.radians(0.267)
+    ss.shadow_cast(out, 5.0, e, a, r, p, mm=mm, out=s, window=win)
+    tsh = min(_timed(lambda: ss.shadow_cast(out, 5.0, e, a, r, p, mm=mm, out=s, window=win), reps))
+    n = W * W
+    return {"work_tile": f"{W}x{W} at 5 m/texel", "sources": "2 x 6144^2 cube-face sub-tiles",
+            "stitch_ms": ms, "uncovered_texels": nan,
+            "stitch_gtexels_s": n / (ms / 1e3) / 1e9,
+            "stitch_gb_s": 8.0 * n / (ms / 1e3) / 1e9,
+            "stitch_frac_of_hbm": 8.0 * n / (ms / 1e3) / 8.0e12,
+            "core_shadow_ms": tsh, "core_mrays_s": 2048 * 2048 / (tsh / 1e3) / 1e6}
+
+
 def leg_batched(ss, reps=3):
     """8 uneven tiles x 64 suns through one captured graph (mipmaps + persistent kernel)."""
     from synth import config, dem_for, sun_list, R_MOON
@@ -708,6 +748,7 @@ def main():
             extras["fwd_bwd_replay_mrays_s" if replay else "fwd_bwd_mrays_s"] = rays_per_step / tfb / 1e6
         extras["differentiable_2048"] = leg_diff(ss)
         extras["frame"] = leg_frame(ss)
+        extras["stitch_across_seam"] = leg_stitch(ss)
         if not args.no_big:
             extras["batched_8x64"] = leg_batched(ss)
             extras["polar_16384"] = leg_polar(ss)

@@ -7,4 +7,4 @@ the HIP path read the arrays it produces; neither side imports the other.
 from .dem import fbm, add_craters, make_dem  # noqa: F401
 from .configs import CONFIGS, config, sun_list, dem_for, seed_of, R_MOON, SUN_RADIUS_RAD  # noqa: F401
 from .configs import look_at, view_scene  # noqa: F401
-from .planet import planet_height, frame_dirs, seam_scene  # noqa: F401
+from .planet import planet_height, frame_dirs, seam_scene, seam_frames  # noqa: F401

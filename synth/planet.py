@@ -62,27 +62,33 @@ def planet_height(dirs: np.ndarray, seed: int, centre, n_bumps: int = 60, extent
     return h.astype(np.float32)
 
 
-def seam_scene(core: int = 256, halo: int = 256, texel_m: float = 10.0, seed: int = 20050699):
-    """Two cube-face sub-tiles meeting at the +z/+x face seam and a working tile tangent on
-    the +z side near it: returns dict(sources=[(heights, frame dict)], work=frame dict,
-    window=(x0, y0, w, h)).  A ridge runs along the +x face 1.5-3 km beyond the seam, so a
-    sun from +x shades the core across the seam."""
+def seam_frames(core: int = 256, halo: int = 256, texel_m: float = 10.0, n_src: int = 1536,
+                offset_m: float = 1.2e3):
+    """Frames of two cube-face sub-tiles (n_src^2 texels) meeting at the +z/+x face seam, and
+    of a working tile (core + 2 halo texels a side) tangent on the +z side, offset_m (surface)
+    from the seam.  The sources reach the seam; the face plane stretches ~1.4x there."""
     R = R_MOON
-    n = 1536  # source tiles: the face plane stretches ~1.4x at the seam (45 deg off-centre)
-    plane = n * texel_m
-    fa = dict(width=n, rows=n, texel_m=texel_m, centre=(0.0, 0.0, 1.0), ex=(1.0, 0.0, 0.0),
-              ey=(0.0, 1.0, 0.0), origin=(R - 0.5 * plane, 0.0))
-    fb = dict(width=n, rows=n, texel_m=texel_m, centre=(1.0, 0.0, 0.0),
+    plane = n_src * texel_m
+    fa = dict(width=n_src, rows=n_src, texel_m=texel_m, centre=(0.0, 0.0, 1.0),
+              ex=(1.0, 0.0, 0.0), ey=(0.0, 1.0, 0.0), origin=(R - 0.5 * plane, 0.0))
+    fb = dict(width=n_src, rows=n_src, texel_m=texel_m, centre=(1.0, 0.0, 0.0),
               ex=(0.0, 0.0, -1.0), ey=(0.0, 1.0, 0.0), origin=(-R + 0.5 * plane, 0.0))
-    seam = unit((1.0, 0.0, 1.0))
-    # working tile centred 1.2 km (surface) on the +z side of the seam
-    rot = 1.2e3 / R
+    rot = offset_m / R
     wc = unit((math.cos(math.pi / 4 + rot), 0.0, math.sin(math.pi / 4 + rot)))
     wx = unit(np.cross((0.0, 1.0, 0.0), wc))
     W = core + 2 * halo
     fw = dict(width=W, rows=W, texel_m=texel_m, centre=tuple(wc), ex=tuple(wx),
               ey=(0.0, 1.0, 0.0), origin=(0.0, 0.0))
-    # ridge across the tile's rows, 1.5-3 km past the seam on the +x face
+    return fa, fb, fw
+
+
+def seam_scene(core: int = 256, halo: int = 256, texel_m: float = 10.0, seed: int = 20050699):
+    """The seam frames with heights from planet_height: a ridge runs along the +x face
+    1.5-3 km beyond the seam, so a sun from +x shades the core across the seam.  Returns
+    dict(sources=[(heights, frame dict)], work=frame dict, window=(x0, y0, w, h))."""
+    R = R_MOON
+    fa, fb, fw = seam_frames(core, halo, texel_m)
+    seam = unit((1.0, 0.0, 1.0))
     d0 = 2.2e3 / R
     rs = unit((math.cos(math.pi / 4 - d0), -3e3 / R, math.sin(math.pi / 4 - d0)))
     re = unit((math.cos(math.pi / 4 - d0), 3e3 / R, math.sin(math.pi / 4 - d0)))
