@@ -13,8 +13,9 @@
 // by the tap-bound pyramid (every bilinear tap of every sample in a level-m
 // cell is at most that cell's entry): the ray is clipped to the tile and to
 // the shell below the highest terrain, then walks the pyramid front to back,
-// skips every cell it passes above (with a margin covering FP32 rounding) and
-// tests grid samples only inside level-0 cells it cannot skip.  Because the
+// skips every cell it passes above (with a margin covering FP32 rounding),
+// moves forward inside a cell to where the ray can first come down to the
+// cell's bound, and tests grid samples only inside level-0 cells.  Because the
 // skip is conservative and the samples are the same, the dense mode (every
 // grid sample between the clip points) gives bit-identical results.
 //
@@ -33,6 +34,7 @@ struct VRay {
   float vx, vy, vz;     // unit direction
   int sgx, sgy;         // motion direction of q along the ray (-1, 0, 1)
   float t_hmin;         // ray length of the lowest point (sphere), or +-inf
+  float b;              // (S0 + eye) . V on the sphere: d|P|/dt = (b + t) / |P|
 };
 
 __device__ __forceinline__ float vbound(const ViewK& K, int m, int cx, int cy) {
@@ -191,8 +193,17 @@ template <bool SPHERE>
 __device__ VHit view_hier(const ViewK& K, const VRay<SPHERE>& r, float t0, float t1,
                           float eyen) {
   VHit h{-1, 0, 0};
-  int m = K.L - 1, cx = 0, cy = 0;
   float t = t0;
+  // start three levels below the top (cells of 1/8 of the tile): every ray
+  // below the shell would descend through the top levels anyway, and after a
+  // skip the walk climbs again where the terrain allows
+  int m = max(K.L - 4, 0), cx = 0, cy = 0;
+  if (m < K.L - 1) {
+    float qx, qy;
+    vq<SPHERE>(K, r, t, qx, qy);
+    cx = min(max((int)floorf(qx * K.inv_pow2[m]), 0), K.lw[m] - 1);
+    cy = min(max((int)floorf(qy * K.inv_pow2[m]), 0), K.lh[m] - 1);
+  }
   for (int it = 0; it < K.max_iter; ++it) {
     h.cells++;
     // exit of the current cell through its far lines in the motion direction
@@ -205,7 +216,18 @@ __device__ VHit view_hier(const ViewK& K, const VRay<SPHERE>& r, float t0, float
     const float tm = fminf(fmaxf(r.t_hmin, t), tb);
     const float Hmin = vH<SPHERE>(K, r, tm);
     const float margin = fmaf(K.m_rel, eyen + tb, K.m_abs);
-    bool pass = Hmin > vbound(K, m, cx, cy) + margin;
+    const float Bm = vbound(K, m, cx, cy) + margin;
+    bool pass = Hmin > Bm;
+    if (!pass) {
+      // the ray's height is convex in t, so its tangent at t is a lower bound:
+      // until the tangent comes down to Bm the ray passes above every tap of
+      // the cell, and those samples are skipped (the slope, (b + t) / |P| on
+      // the sphere, carries an allowance for its FP32 error of ~1e-7)
+      const float Ht = vH<SPHERE>(K, r, t);
+      const float slope = SPHERE ? (r.b + t) / (K.R + Ht) : r.vz;
+      const float rate = 2e-7f - slope;
+      if (Ht > Bm && rate > 0.0f) t = fminf(t + (Ht - Bm) / rate, tb);
+    }
     if (!pass && m > 0) {
       // descend into the child that holds q(t) (clamped to this cell)
       float qx, qy;
@@ -279,7 +301,8 @@ __global__ __launch_bounds__(256) void view_kernel(ViewK K, float* __restrict__ 
     float tpz = INFINITY;
     if (SPHERE) {
       if (r.vz < 0.0f) tpz = (0.5f * K.R + r.ez) / -r.vz;
-      r.t_hmin = -fmaf(K.R, r.vz, fmaf(r.ex, r.vx, fmaf(r.ey, r.vy, r.ez * r.vz)));
+      r.b = fmaf(K.R, r.vz, fmaf(r.ex, r.vx, fmaf(r.ey, r.vy, r.ez * r.vz)));
+      r.t_hmin = -r.b;
     } else {
       r.t_hmin = r.vz < 0.0f ? INFINITY : -INFINITY;
     }
