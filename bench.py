@@ -578,6 +578,10 @@ def leg_polar(ss, reps=3):
     return res
 
 
+LEGS = {"frame": lambda ss: leg_frame(ss), "stitch": lambda ss: leg_stitch(ss),
+        "diff": lambda ss: leg_diff(ss)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -595,9 +599,15 @@ def main():
                     help="load the DEM from this .npy if present, else generate and save it")
     ap.add_argument("--summarize", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COUNTERS", "OUT"),
                     help="write profile summaries from rocprofv3 CSV directories and exit")
+    ap.add_argument("--leg", action="append", choices=sorted(LEGS),
+                    help="run only this extra leg (repeatable) and print its JSON; for profiling")
     args = ap.parse_args()
     if args.summarize:
         summarize_profiles(*args.summarize)
+        return
+    if args.leg:
+        import paper_2005_06671_amd as ss
+        print(json.dumps({name: LEGS[name](ss) for name in args.leg}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the path would "
