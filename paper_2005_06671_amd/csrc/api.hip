@@ -696,12 +696,24 @@ static std::string tune_key(const ss_tile* tiles, int n_tiles, int n_suns, const
   return k + buf;
 }
 
-static double time_ms(hipStream_t s, hipEvent_t a, hipEvent_t b) {
+// Milliseconds between two recorded events; a HIP error comes back as such.
+static hipError_t time_ms(hipEvent_t a, hipEvent_t b, double* out) {
   float ms = 0.0f;
-  hipEventSynchronize(b);
-  hipEventElapsedTime(&ms, a, b);
-  return ms;
+  hipError_t e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+  *out = ms;
+  return e;
 }
+
+// Two timing events, released on every path out of the tuner (a destructor
+// cannot report the release's own status, so that one is dropped).
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
 
 // Times each ray-tile shape on the largest tile with its middle sun, and each
 // fusion depth on that tile's mipmap; the choices never change results.
@@ -712,9 +724,10 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
   for (int t = 1; t < n_tiles; ++t)
     if ((int64_t)tiles[t].width * tiles[t].rows > (int64_t)tiles[big].width * tiles[big].rows) big = t;
   const int ks = n_suns / 2;
-  hipEvent_t a, b;
-  SS_HIP(hipEventCreate(&a));
-  SS_HIP(hipEventCreate(&b));
+  EventPair ev;
+  SS_HIP(hipEventCreate(&ev.a));
+  SS_HIP(hipEventCreate(&ev.b));
+  const hipEvent_t a = ev.a, b = ev.b;
   float* out = d_shadow[(size_t)big * n_suns + ks];
   // fusion depth
   double best = 1e30;
@@ -727,7 +740,8 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
                                 const_cast<float*>(tiles[big].maxmip), f, s);
       if (rc) return rc;
       SS_HIP(hipEventRecord(b, s));
-      const double ms = time_ms(s, a, b);
+      double ms = 0.0;
+      SS_HIP(time_ms(a, b, &ms));
       if (rep > 0 && ms < best) {
         best = ms;
         *best_fuse = f;
@@ -748,15 +762,14 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
       SS_HIP(hipEventRecord(a, s));
       SS_HIP(launch_forward(K, r2.sphere, r2.mode, sh, false, out, nullptr, nullptr, s));
       SS_HIP(hipEventRecord(b, s));
-      const double ms = time_ms(s, a, b);
+      double ms = 0.0;
+      SS_HIP(time_ms(a, b, &ms));
       if (rep > 0 && ms < best) {
         best = ms;
         *best_tile = sh;
       }
     }
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
   return SS_OK;
 }
 
@@ -840,7 +853,8 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
   } else {
     rc = hip_fail(e);
   }
-  hipStreamDestroy(cs);
+  const hipError_t ed = hipStreamDestroy(cs);
+  if (rc == SS_OK && ed != hipSuccess) rc = hip_fail(ed);
   if (rc != SS_OK) {
     ss_batched_plan_destroy(plan);
     return rc;
@@ -864,9 +878,12 @@ extern "C" int32_t ss_batched_plan_config(const ss_plan* plan, int32_t* ray_tile
 
 extern "C" int32_t ss_batched_plan_destroy(ss_plan* plan) {
   if (!plan) return SS_OK;
-  if (plan->exec) hipGraphExecDestroy(plan->exec);
-  if (plan->graph) hipGraphDestroy(plan->graph);
-  delete plan;
+  hipError_t e = hipSuccess, e2 = hipSuccess;
+  if (plan->exec) e = hipGraphExecDestroy(plan->exec);
+  if (plan->graph) e2 = hipGraphDestroy(plan->graph);
+  delete plan;  // released either way: a failed destroy leaves nothing to retry with
+  if (e != hipSuccess) return hip_fail(e);
+  if (e2 != hipSuccess) return hip_fail(e2);
   return SS_OK;
 }
 

@@ -171,3 +171,22 @@ def test_view_edges(ss):
     zero = dict(base, fwd=(0.3, 0.0, -0.6), right=(0.6, 0.0, -1.2))
     t5, xy5 = run(ss, h, 10.0, zero, math.inf, ss.SS_VIEW_HIER)
     assert np.isinf(t5[0, 0]) and np.isnan(xy5[0, 0]).all() and np.isfinite(t5[0, 1])
+
+
+@pytest.mark.parametrize("alt_km,hfov", [(100.0, 14.0), (30.0, 40.0), (8.0, 75.0), (1.5, 90.0)])
+def test_view_descent_trajectory(ss, diff, alt_km, hfov):
+    """A descent toward the 2048^2 tile over two orders of magnitude of distance (the paper
+    flies a trajectory covering more than 100 km of altitude, Sec. 6.3): the eye on a line
+    40 deg above the horizon through the tile centre, field of view narrowing with distance."""
+    from synth.configs import look_at
+    alt = alt_km * 1e3
+    back = alt / math.tan(math.radians(40.0))
+    cam = look_at((-back * 0.8, -back * 0.6, alt), (0.0, 0.0, 0.0), hfov, 64, 48, 5.0)
+    print(f"trajectory {alt_km} km", flush=True)
+    t, xy = run(ss, diff, 10.0, cam, R, ss.SS_VIEW_HIER)
+    td, xyd = run(ss, diff, 10.0, cam, R, ss.SS_VIEW_DENSE)
+    assert np.array_equal(bits(t), bits(td)) and np.array_equal(bits(xy), bits(xyd))
+    stats = view_parity.check(diff, R, 10.0, oracle.Camera(**cam), t, xy,
+                              label=f"{alt_km} km")
+    print(stats)
+    assert stats["exact"] > 500
