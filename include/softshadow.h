@@ -289,7 +289,12 @@ int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_s
  * ray-tile shape and mipmap fusion depth by timing the candidates on these
  * inputs (it synchronises `stream` while tuning), then captures the maxmip
  * builds and the persistent launch.  Launch replays the graph on `stream`; the
- * workspace belongs to the plan until it is destroyed. */
+ * workspace belongs to the plan until it is destroyed.  Choices are kept per
+ * process, keyed by the device architecture, the tile sizes and spacings, the
+ * sun count and the method parameters; with the environment variable
+ * SS_TUNE_CACHE naming a file they also persist across processes (read once,
+ * new choices appended as JSON lines {"key": ..., "ray_tile": n,
+ * "fuse_depth": f}).  The choices never change results. */
 typedef struct ss_plan ss_plan;
 int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
                                int32_t n_suns, const ss_params* params, float* const* d_shadow,

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <map>
@@ -681,10 +682,52 @@ struct TuneKey {
 static std::mutex g_tune_mu;
 static std::map<TuneKey, std::pair<int, int>> g_tune;
 
+// Persistent tuner results: with SS_TUNE_CACHE naming a file, choices are read
+// from it once per process and each new one is appended, one JSON object per
+// line: {"key": "...", "ray_tile": n, "fuse_depth": f}.  Keys start with the
+// device's architecture name.  Unreadable lines and out-of-range choices are
+// ignored (the tuner then runs again); the choices never change results.
+static std::once_flag g_tune_file_once;
+
+static void tune_file_load() {
+  const char* path = getenv("SS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[1024], key[900];
+  int rt = 0, fd = 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  while (fgets(line, sizeof line, f)) {
+    if (sscanf(line, " {\"key\": \"%899[^\"]\", \"ray_tile\": %d, \"fuse_depth\": %d}", key, &rt,
+               &fd) != 3)
+      continue;
+    if (rt < SS_TILE_8x8 || rt > SS_TILE_32x2 || fd < 1 || fd > 6) continue;
+    g_tune.emplace(TuneKey{key}, std::make_pair(rt, fd));
+  }
+  fclose(f);
+}
+
+static void tune_file_append(const std::string& key, int rt, int fd) {
+  const char* path = getenv("SS_TUNE_CACHE");
+  if (!path || !*path || key.size() >= 900 || key.find('"') != std::string::npos) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"ray_tile\": %d, \"fuse_depth\": %d}\n", key.c_str(), rt, fd);
+  fclose(f);
+}
+
+static std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  return std::string(prop.gcnArchName);
+}
+
 static std::string tune_key(const ss_tile* tiles, int n_tiles, int n_suns, const Resolved& rp,
                             const ss_params* p) {
   char buf[128];
-  std::string k;
+  std::string k = arch_name() + "|";
   snprintf(buf, sizeof buf, "m%d s%d n%d g%d q%d r%.3g c%.3g|", rp.mode, rp.sphere, rp.n_prime0,
            rp.schedule, rp.prune, p->body_radius_m, p->max_len_m);
   k += buf;
@@ -802,6 +845,7 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
   int tile_code = params->ray_tile, fuse = 6;
   const std::string key = tune_key(tiles, n_tiles, n_suns, rp, params);
   bool cached = false;
+  std::call_once(g_tune_file_once, tune_file_load);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(TuneKey{key});
@@ -818,6 +862,7 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune[TuneKey{key}] = {bt_code, bf};
+      tune_file_append(key, bt_code, bf);
     }
     if (!tile_code) tile_code = bt_code;
     fuse = bf;

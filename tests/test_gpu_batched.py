@@ -114,3 +114,45 @@ def test_full_batched_workload(ss):
                      label=f"batched tile{t} sun{k}")
         assert_parity(st)
     plan.close()
+
+
+def test_tuner_choices_persist_across_processes(tmp_path):
+    """SS_TUNE_CACHE: a first process tunes and appends its choice; a second process with
+    the file edited to another valid choice takes that one without tuning, and its outputs
+    are bitwise those of the first (choices never change results)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.jsonl"
+    out = tmp_path / "s.npy"
+    prog = (
+        "import sys, numpy as np, torch\n"
+        "sys.path.insert(0, %r)\n"
+        "import paper_2005_06671_amd as ss, synth\n"
+        "hs = [synth.dem_for('small', device='cuda'), synth.dem_for('small', device='cuda')[:200, :160].contiguous()]\n"
+        "suns = synth.sun_list('batched')[:4]\n"
+        "plan = ss.BatchedPlan(hs, [20.0, 15.0], suns, ss.Params(radius_m=synth.R_MOON))\n"
+        "plan.launch(); torch.cuda.synchronize()\n"
+        "print('CONFIG', *plan.config())\n"
+        "np.save(sys.argv[1], np.concatenate([o.cpu().numpy().ravel() for row in plan.outs for o in row]))\n"
+    ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, SS_TUNE_CACHE=str(cache))
+    r1 = subprocess.run([sys.executable, "-c", prog, str(out)], env=env, capture_output=True,
+                        text=True, timeout=240)
+    assert r1.returncode == 0, r1.stderr[-2000:]
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert rec["key"].startswith("gfx") and 1 <= rec["ray_tile"] <= 4 and 1 <= rec["fuse_depth"] <= 6
+    s1 = np.load(out)
+    other = {"ray_tile": 4 if rec["ray_tile"] != 4 else 1,
+             "fuse_depth": 3 if rec["fuse_depth"] != 3 else 5}
+    cache.write_text(json.dumps({"key": rec["key"], **other}) + "\n")
+    r2 = subprocess.run([sys.executable, "-c", prog, str(out)], env=env, capture_output=True,
+                        text=True, timeout=240)
+    assert r2.returncode == 0, r2.stderr[-2000:]
+    cfg = [ln for ln in r2.stdout.splitlines() if ln.startswith("CONFIG")][0].split()[1:]
+    assert [int(v) for v in cfg] == [other["ray_tile"], other["fuse_depth"]]
+    assert len(cache.read_text().splitlines()) == 1  # nothing tuned, nothing appended
+    assert np.array_equal(np.load(out).view(np.uint32), s1.view(np.uint32))
