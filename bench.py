@@ -732,6 +732,16 @@ def main():
             _, cnt = ss.shadow_cast_counted(h, D, e, a, r, pu, mm=mm)
             ucnt.append(int(cnt[1].item()))
         extras["uniform_steps_per_ray"] = float(np.mean(ucnt)) / (W * H)
+        # the same-accuracy comparison: the exact mode (descent as incumbent, then
+        # branch and bound over the max-mip tap-bound pyramid) returns the dense
+        # half-texel stepping result bit for bit; one-texel stepping is coarser
+        # than both (its error against dense is in accuracy_vs_dense)
+        ex = extras["exact_mode"]
+        extras["equal_accuracy"] = {
+            "exact_over_dense_uniform_identical_output": ex["speedup_vs_dense"],
+            "exact_over_uniform_1_texel": ex["mrays_s"] / uniform,
+            "exact_bit_identical_to_dense": ex["bit_identical_to_dense"],
+            "uniform_1_texel_mean_abs_error": extras["accuracy_vs_dense"]["uniform_1_texel"]["mean_abs"]}
         # forward + backward (hand-written adjoint) for every sun: the recorded
         # forward with the adjoint reading the record, and the replaying adjoint
         g = torch.randn(H, W, generator=torch.Generator(device="cpu").manual_seed(7)).to(dev)
