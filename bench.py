@@ -529,9 +529,17 @@ def leg_batched(ss, reps=3):
     rays = sum(w * r for (w, r, _) in c["tiles"]) * len(suns)
     rt, fd = plan.config()
     plan.close()
+    del plan
+    # the exact mode over the same batch (tap-bound pyramids rebuilt in the graph)
+    plan = ss.BatchedPlan(heights, texels, suns,
+                          ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_EXACT))
+    plan.launch()
+    tx = _timed(plan.launch, 1)
+    plan.close()
     del plan, heights
     return {"rays": rays, "graph_launch_ms": min(ts), "mrays_s": rays / (min(ts) / 1e3) / 1e6,
-            "ray_tile": rt, "fuse_depth": fd}
+            "ray_tile": rt, "fuse_depth": fd, "exact_graph_launch_ms": min(tx),
+            "exact_mrays_s": rays / (min(tx) / 1e3) / 1e6}
 
 
 def leg_polar(ss, reps=3):

@@ -280,7 +280,8 @@ int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns);
  * k in one persistent launch that takes (tile, sun, ray block) items from a
  * queue in d_workspace.  Outputs are bit-identical to ss_shadow_cast with the
  * same parameters.  d_workspace is used for the duration of the call.
- * SS_MODE_DP, SS_MODE_UNIFORM and SS_MODE_POINT (SS_MODE_EXACT: SS_ERR_UNSUPPORTED). */
+ * Every mode; SS_MODE_EXACT needs each tile's `bound` buffer, which the call
+ * (and a plan's graph) rebuilds from the heights like the maximum mipmap. */
 int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
                                int32_t n_suns, const ss_params* params, float* const* d_shadow,
                                void* d_workspace, int64_t workspace_bytes, void* stream);

@@ -472,13 +472,14 @@ def shadow(h, elev, azim, texel_m, ang_radius=SUN_RADIUS_RAD, params: Params | N
 # Batched form
 # ---------------------------------------------------------------------------
 
-def _batch_structs(heights, mms, texels, suns, windows=None):
+def _batch_structs(heights, mms, texels, suns, windows=None, bounds=None):
     nt = len(heights)
     tiles = (L.SSTile * max(1, nt))()
     windows = windows or [None] * nt
+    bounds = bounds or [None] * nt
     for k, (h, mm, tx) in enumerate(zip(heights, mms, texels)):
         _dev_f32_2d(h, f"heights[{k}]")
-        tiles[k] = _tile(h, mm, tx, None, windows[k])
+        tiles[k] = _tile(h, mm, tx, bounds[k], windows[k])
     ns = len(suns)
     ss = (L.SSSun * max(1, ns))()
     for k, sun in enumerate(suns):
@@ -512,18 +513,28 @@ def _alloc_batch(heights, suns, outs, mms, windows=None):
     return mms, outs, ptrs, ws
 
 
+def _bounds_for(heights, params, bounds):
+    """Tap-bound buffers for the exact mode (the batched call fills them)."""
+    if bounds is None and params.mode == L.SS_MODE_EXACT:
+        bounds = [torch.empty(max(1, bound_floats(h.shape[1], h.shape[0])), dtype=torch.float32,
+                              device=h.device) for h in heights]
+    return bounds
+
+
 def shadow_cast_batched(heights, texels, suns, params: Params | None = None, outs=None, mms=None,
-                        windows=None):
+                        windows=None, bounds=None):
     """s for every (tile, sun): returns outs[t][k] (float32, shape of tile t or
     of its ray window).
 
-    Builds every tile's mipmap and runs one persistent launch over all items.
+    Builds every tile's mipmap (and, in the exact mode, its tap-bound pyramid
+    into ``bounds``) and runs one persistent launch over all items.
     """
     params = params or Params()
     if len(heights) == 0 or len(suns) == 0:
         return [[] for _ in heights]
     mms, outs, ptrs, ws = _alloc_batch(heights, suns, outs, mms, windows)
-    tiles, ss = _batch_structs(heights, mms, texels, suns, windows)
+    bounds = _bounds_for(heights, params, bounds)
+    tiles, ss = _batch_structs(heights, mms, texels, suns, windows, bounds)
     p = params.c()
     L.check("ss_shadow_cast_batched",
             L.lib().ss_shadow_cast_batched(tiles, len(heights), ss, len(suns), C.byref(p),
@@ -536,12 +547,14 @@ class BatchedPlan:
     """Captured HIP graph of the batched call for fixed buffers (tuned at creation)."""
 
     def __init__(self, heights, texels, suns, params: Params | None = None, outs=None, mms=None,
-                 windows=None):
+                 windows=None, bounds=None):
         self.params = params or Params()
         self.heights = list(heights)
         self.mms, self.outs, self._ptrs, self.ws = _alloc_batch(self.heights, suns, outs, mms,
                                                                 windows)
-        self._tiles, self._suns = _batch_structs(self.heights, self.mms, texels, suns, windows)
+        self.bounds = _bounds_for(self.heights, self.params, bounds)
+        self._tiles, self._suns = _batch_structs(self.heights, self.mms, texels, suns, windows,
+                                                 self.bounds)
         self._p = self.params.c()
         handle = C.c_void_p()
         L.check("ss_batched_plan_create",

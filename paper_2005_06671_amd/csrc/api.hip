@@ -597,7 +597,6 @@ static int32_t check_batch(const ss_tile* tiles, int32_t n_tiles, const ss_sun* 
   Resolved rp;
   int32_t rc = resolve_params(params, &rp);
   if (rc) return rc;
-  if (rp.mode == SS_MODE_EXACT) return SS_ERR_UNSUPPORTED;
   for (int t = 0; t < n_tiles; ++t) {
     if ((rc = check_tile(&tiles[t], rp.mode))) return rc;
     if (tiles[t].width == 0 || tiles[t].rows == 0) return SS_ERR_INVALID_ARG;
@@ -627,6 +626,11 @@ static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchT
     int32_t rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows,
                               const_cast<float*>(tiles[t].maxmip), fuse, stream);
     if (rc) return rc;
+    // the exact mode also reads each tile's tap-bound pyramid (sun-independent)
+    if (bt.rp.mode == SS_MODE_EXACT &&
+        (rc = ss_bound_build(tiles[t].height, tiles[t].width, tiles[t].rows,
+                             const_cast<float*>(tiles[t].bound), stream)))
+      return rc;
   }
   SS_HIP(launch_fill_u32(reinterpret_cast<unsigned int*>(ws + L.counter), 0u, 1, stream));
   SS_HIP(launch_batched(reinterpret_cast<const TileK*>(ws + L.pairs),
@@ -836,11 +840,15 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
   hipStream_t s = (hipStream_t)stream;
   Resolved rp;
   resolve_params(params, &rp);
-  // tune (mipmaps first: the ray kernels read them)
+  // tune (mipmaps and tap-bound pyramids first: the ray kernels read them)
   for (int t = 0; t < n_tiles; ++t) {
     rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows,
                       const_cast<float*>(tiles[t].maxmip), 6, s);
     if (rc) return rc;
+    if (rp.mode == SS_MODE_EXACT &&
+        (rc = ss_bound_build(tiles[t].height, tiles[t].width, tiles[t].rows,
+                             const_cast<float*>(tiles[t].bound), s)))
+      return rc;
   }
   int tile_code = params->ray_tile, fuse = 6;
   const std::string key = tune_key(tiles, n_tiles, n_suns, rp, params);

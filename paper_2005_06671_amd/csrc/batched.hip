@@ -101,6 +101,7 @@ static hipError_t launch_bs(const TileK* a, float* const* b, const long long* c,
   switch (mode) {
     case SS_MODE_UNIFORM: return launch_bm<SPHERE, SS_MODE_UNIFORM>(a, b, c, d, e, bd, ray_tile, n_wg, s);
     case SS_MODE_POINT: return launch_bm<SPHERE, SS_MODE_POINT>(a, b, c, d, e, bd, ray_tile, n_wg, s);
+    case SS_MODE_EXACT: return launch_bm<SPHERE, SS_MODE_EXACT>(a, b, c, d, e, bd, ray_tile, n_wg, s);
     default: return launch_bm<SPHERE, SS_MODE_DP>(a, b, c, d, e, bd, ray_tile, n_wg, s);
   }
 }
@@ -131,6 +132,7 @@ static const void* kernel_of_mode(int mode, int tw) {
   switch (mode) {
     case SS_MODE_UNIFORM: return kernel_of<SPHERE, SS_MODE_UNIFORM>(tw);
     case SS_MODE_POINT: return kernel_of<SPHERE, SS_MODE_POINT>(tw);
+    case SS_MODE_EXACT: return kernel_of<SPHERE, SS_MODE_EXACT>(tw);
     default: return kernel_of<SPHERE, SS_MODE_DP>(tw);
   }
 }

@@ -137,8 +137,10 @@ int main(void) {
          SS_ERR_INVALID_ARG);
   q = p;
   q.mode = SS_MODE_EXACT;
+  tiles[1].bound = NULL;  /* the exact mode needs every tile's tap-bound buffer */
   EXPECT(ss_shadow_cast_batched(tiles, 2, suns, 2, &q, (float* const*)outs, FAKE(0x800000), ws,
-                                NULL) == SS_ERR_UNSUPPORTED);
+                                NULL) == SS_ERR_INVALID_ARG);
+  tiles[1].bound = FAKE(0x300000);
   ss_plan* plan = NULL;
   EXPECT(ss_batched_plan_create(tiles, 2, suns, 2, &p, (float* const*)outs, FAKE(0x800000), ws - 1,
                                 NULL, &plan) == SS_ERR_WORKSPACE);

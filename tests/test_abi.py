@@ -140,13 +140,16 @@ def test_batched_validation(L):
                                       None) == L.SS_ERR_INVALID_ARG
     assert lib.ss_batched_plan_launch(None, None) == L.SS_ERR_INVALID_ARG
     assert lib.ss_batched_plan_destroy(None) == 0
-    # the exact mode is per tile only
+    # the exact mode needs every tile's tap-bound buffer
     outs[4] = 0x600000
     p.mode = L.SS_MODE_EXACT
-    t.bound = 0x800000
-    tiles = (L.SSTile * 2)(t, t)
+    t2 = L.SSTile.from_buffer_copy(t)
+    t2.bound = 0x800000
+    tiles = (L.SSTile * 2)(t2, t)
     assert lib.ss_shadow_cast_batched(tiles, 2, suns, 3, C.byref(p), outs, 0x700000, need,
-                                      None) == L.SS_ERR_UNSUPPORTED
+                                      None) == L.SS_ERR_INVALID_ARG
+    assert lib.ss_batched_plan_create(tiles, 2, suns, 3, C.byref(p), outs, 0x700000, need, None,
+                                      C.byref(plan)) == L.SS_ERR_INVALID_ARG
 
 
 def test_probe_validation(L):

@@ -49,7 +49,7 @@ def same(a, b):
     return torch.equal(a.view(torch.int32), b.view(torch.int32))
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_batched_equals_per_tile(ss, mode):
     hs, texels, suns = small_batch()
     params = ss.Params(radius_m=R, max_len_m=2500.0, mode=mode)
@@ -63,9 +63,10 @@ def test_batched_equals_per_tile(ss, mode):
                 assert same(got[t][k], ref[t][k]), (mode, tile, t, k)
 
 
-def test_graph_plan_replays(ss):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_graph_plan_replays(ss, mode):
     hs, texels, suns = small_batch()
-    params = ss.Params(radius_m=R, max_len_m=2500.0)
+    params = ss.Params(radius_m=R, max_len_m=2500.0, mode=mode)
     ref = per_tile(ss, hs, texels, suns, params)
     plan = ss.BatchedPlan(hs, texels, suns, params)
     rt, fd = plan.config()
