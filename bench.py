@@ -586,8 +586,28 @@ def leg_polar(ss, reps=3):
     return res
 
 
+def leg_exact(ss, reps=2):
+    """The exact mode alone on the 4096^2 tile, all 8 suns: launch times, rays/s and the
+    units per ray (for profiling its kernel)."""
+    import torch
+    from synth import config, dem_for, sun_list, R_MOON
+    c = config("tile")
+    W, H, D = c["tiles"][0]
+    h = dem_for("tile", device="cuda")
+    mm = ss.maxmip(h)
+    bound = ss.bound_build(h)
+    out = torch.empty_like(h)
+    p = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_EXACT)
+    ts = []
+    for (e, a, r) in sun_list("tile"):
+        ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out, bound=bound)
+        ts.append(min(_timed(lambda: ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out,
+                                                    bound=bound), reps)))
+    return {"launch_ms": ts, "mrays_s": W * H * len(ts) / (sum(ts) / 1e3) / 1e6}
+
+
 LEGS = {"frame": lambda ss: leg_frame(ss), "stitch": lambda ss: leg_stitch(ss),
-        "diff": lambda ss: leg_diff(ss)}
+        "diff": lambda ss: leg_diff(ss), "exact": lambda ss: leg_exact(ss)}
 
 
 def main():

@@ -671,6 +671,10 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
   // where the samples end: the cap, or the tile edge
   const float uend = fminf(r.uexit, t_to_u(r, T.ucap));
   int n = 0, m = 0;
+  // the level-0 texel whose test last failed: its next sample is evaluated
+  // without testing again (a test only ever skips work, so this changes no
+  // result; the texel's second sample rarely clears where the first did not)
+  int fx0 = -1, fy0 = -1;
   const bool umbra = T.prune && best <= -T.tan_rL;  // settled by the descent
   for (int it = 0; it < (umbra ? 0 : (1 << 24)); ++it) {
     const float t = step_t(T, n, T.half_delta);
@@ -682,7 +686,7 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
     const int iy = min(max((int)floorf((float)r.j + 0.5f + r.oy + r.Ky * u), 0), T.H - 1);
     const int cx = ix >> m, cy = iy >> m;
     bool skip = false;
-    if (T.prune) {
+    if (T.prune && !(m == 0 && ix == fx0 && iy == fy0)) {
       n_tst++;
       // relative to the origin the bound must be at least 0 (see clears)
       const float b0 = fmaxf(bound_at(T, m, cx, cy) - r.hp, 0.0f);
@@ -701,6 +705,8 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
     } else if (m > 0) {
       --m;
     } else {
+      fx0 = ix;
+      fy0 = iy;
       const Sample s = sample_at(r, T, t, u);
       n_smp++;
       float num, den;
