@@ -31,14 +31,19 @@ __global__ __launch_bounds__(256) void batched_kernel(const TileK* __restrict__ 
                                                       long long item_limit, int n_pairs) {
   constexpr int TH = 64 / TW;
   __shared__ unsigned int s_item;
+  __shared__ int tab[SS_MAXLEV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
     __syncthreads();
     const long long item = (long long)s_item;
+    // every thread is past the previous item here, so the table can be refilled
+    const int pair = item < item_limit
+                         ? __builtin_amdgcn_readfirstlane(pair_of(item_start, n_pairs, item))
+                         : 0;
+    if (MODE == SS_MODE_EXACT && item < item_limit) bound_tab_fill(pairs[pair], tab);
     __syncthreads();
     if (item >= item_limit) break;
-    const int pair = __builtin_amdgcn_readfirstlane(pair_of(item_start, n_pairs, item));
     const TileK& T = pairs[pair];
     float* out = outs[pair];
     const int nbx = pair_nbx[pair];
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(256) void batched_kernel(const TileK* __restrict__ 
         Ray<SPHERE> r;
         ray_init(T, i, j, hp, r);
         unsigned n_lb = 0, n_smp = 0;
-        const float alpha = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp).alpha;
+        const float alpha = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab).alpha;
         out[lj * T.RW + li] = disc_fraction(alpha, T);
       }
     }

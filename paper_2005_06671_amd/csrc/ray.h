@@ -620,8 +620,15 @@ __device__ __forceinline__ RayResult shadow_uniform(const TileK& T, const Ray<SP
 // Entry m >= 0 of the tap-bound pyramid: the largest height any bilinear tap
 // of a sample inside level-m texel (cx, cy) can read (also for samples up to
 // half a texel outside it).
-__device__ __forceinline__ float bound_at(const TileK& T, int m, int cx, int cy) {
-  const float* base = m == 0 ? T.bnd : T.bmm + T.loff[m];
+// The exact walk's pyramid level differs between lanes, so reading the level's
+// offset from the kernel arguments would put a dependent memory load before
+// every bound; kernels that run the walk copy the offsets to LDS first.
+__device__ __forceinline__ void bound_tab_fill(const TileK& T, int* tab) {
+  if (threadIdx.x < SS_MAXLEV) tab[threadIdx.x] = T.loff[threadIdx.x];
+}
+
+__device__ __forceinline__ float bound_at(const TileK& T, const int* tab, int m, int cx, int cy) {
+  const float* base = m == 0 ? T.bnd : T.bmm + tab[m];
   const int w = (T.W + (1 << m) - 1) >> m;
   return base[idx2((unsigned)cy, (unsigned)w, (unsigned)cx)];
 }
@@ -648,7 +655,8 @@ __device__ __forceinline__ float bound_at(const TileK& T, int m, int cx, int cy)
 // the descent already finds in umbra is then done.
 template <bool SPHERE>
 __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHERE>& r, float top,
-                                                  unsigned& n_tst, unsigned& n_smp) {
+                                                  unsigned& n_tst, unsigned& n_smp,
+                                                  const int* tab) {
   RayResult res;
   res.t = 0.0f;
   res.u = 0.0f;
@@ -689,7 +697,7 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
     if (T.prune && !(m == 0 && ix == fx0 && iy == fy0)) {
       n_tst++;
       // relative to the origin the bound must be at least 0 (see clears)
-      const float b0 = fmaxf(bound_at(T, m, cx, cy) - r.hp, 0.0f);
+      const float b0 = fmaxf(bound_at(T, tab, m, cx, cy) - r.hp, 0.0f);
       const float top = r.dz > b0 ? r.dz : b0;
       skip = clears(r, T, t, top, need);
     }
@@ -732,11 +740,11 @@ __device__ __forceinline__ RayResult shadow_exact(const TileK& T, const Ray<SPHE
 // The shadow clearance of one ray by the chosen method.
 template <bool SPHERE, int MODE>
 __device__ __forceinline__ RayResult trace_ray(const TileK& T, const Ray<SPHERE>& r, unsigned& n_lb,
-                                               unsigned& n_smp) {
+                                               unsigned& n_smp, const int* tab) {
   // no terrain rises above `top` (relative to h_p, at least 0)
   const float t0 = T.prune ? fmaxf(mip_at(T, T.L - 1, 0, 0), r.hp) - r.hp : 0.0f;
   const float top = r.dz > t0 ? r.dz : t0;
-  if (MODE == SS_MODE_EXACT) return shadow_exact(T, r, top, n_lb, n_smp);
+  if (MODE == SS_MODE_EXACT) return shadow_exact(T, r, top, n_lb, n_smp, tab);
   if (MODE == SS_MODE_POINT) return shadow_dp<SPHERE, true>(T, r, top, n_lb, n_smp);
   if (MODE == SS_MODE_UNIFORM) return shadow_uniform(T, r, top, n_smp);
   return shadow_dp<SPHERE, false>(T, r, top, n_lb, n_smp);

@@ -52,6 +52,11 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
                                                      int* __restrict__ sample, int nbx,
                                                      int nblocks) {
   constexpr bool COUNT = FLAGS == FWD_COUNT;
+  __shared__ int tab[SS_MAXLEV];
+  if (MODE == SS_MODE_EXACT) {
+    bound_tab_fill(T, tab);
+    __syncthreads();
+  }
   int li, lj;
   ray_coords<TW>(nbx, nblocks, li, lj);
   unsigned n_lb = 0, n_smp = 0;
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
-    const RayResult res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp);
+    const RayResult res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab);
     out[lj * T.RW + li] = disc_fraction(res.alpha, T);
     if (FLAGS == FWD_SAVE) sample[lj * T.RW + li] = res.valid ? res.n : -1;
   }
@@ -87,7 +92,8 @@ template <bool SPHERE, int MODE, bool SAVED>
 __device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, int li, int lj,
                                             const float* __restrict__ gs,
                                             const int* __restrict__ sample,
-                                            float* __restrict__ gh, double& ge, double& ga) {
+                                            float* __restrict__ gh, double& ge, double& ga,
+                                            const int* tab) {
   if (li < T.RW && lj < T.RH) {
     const int i = T.rx0 + li, j = T.ry0 + lj;
     const float g = gs[lj * T.RW + li];
@@ -111,7 +117,7 @@ __device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, i
       }
     } else {
       unsigned n_lb = 0, n_smp = 0;
-      res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp);
+      res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab);
     }
     const float dd = res.alpha * T.inv_rL;
     if (res.valid && g != 0.0f && fabsf(dd) < 1.0f) {
@@ -241,6 +247,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
                                                       double* __restrict__ gsun, int nbx,
                                                       int nblocks) {
   __shared__ double red[2][4];
+  __shared__ int tab[SS_MAXLEV];
+  if (MODE == SS_MODE_EXACT && !SAVED) {
+    bound_tab_fill(T, tab);
+    __syncthreads();
+  }
   double ge = 0.0, ga = 0.0;
   const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   for (int g = 0; g < AdjBlocks<SAVED>::n; ++g) {
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
     if (vb >= nblocks) break;
     int i, j;
     coords_of<TW>(vb, nbx, i, j);
-    adjoint_ray<SPHERE, MODE, SAVED>(T, st, i, j, gs, sample, gh, ge, ga);
+    adjoint_ray<SPHERE, MODE, SAVED>(T, st, i, j, gs, sample, gh, ge, ga, tab);
   }
   ge = wave_sum_f64(ge);
   ga = wave_sum_f64(ga);
@@ -273,6 +284,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
 template <bool SPHERE, int MODE>
 __global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __restrict__ xy,
                                                      long long n, float* __restrict__ out) {
+  __shared__ int tab[SS_MAXLEV];
+  if (MODE == SS_MODE_EXACT) {
+    bound_tab_fill(T, tab);
+    __syncthreads();
+  }
   const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
   const float2 q = xy[k];
@@ -288,7 +304,7 @@ __global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __re
   ray_init(T, i, j, ref, r, qx - ((float)i + 0.5f), qy - ((float)j + 0.5f),
            terrain_above(T, qx, qy, ref));
   unsigned n_lb = 0, n_smp = 0;
-  out[k] = disc_fraction(trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp).alpha, T);
+  out[k] = disc_fraction(trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab).alpha, T);
 }
 
 template <bool SPHERE, int MODE>
