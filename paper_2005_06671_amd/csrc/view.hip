@@ -37,9 +37,27 @@ struct VRay {
   float b;              // (S0 + eye) . V on the sphere: d|P|/dt = (b + t) / |P|
 };
 
-__device__ __forceinline__ float vbound(const ViewK& K, int m, int cx, int cy) {
-  const float* base = m == 0 ? K.bnd : K.bmm + K.loff[m];
-  return base[__umul24((unsigned)cy, (unsigned)K.lw[m]) + (unsigned)cx];
+// Per-level tables in LDS: the walk's level differs between lanes, and
+// indexing the kernel arguments with it would put a dependent memory load in
+// front of every bound.
+struct VTab {
+  int off[SS_MAXLEV], lw[SS_MAXLEV], lh[SS_MAXLEV];
+  float ip[SS_MAXLEV];  // 2^-m
+};
+
+__device__ __forceinline__ void vtab_fill(const ViewK& K, VTab& lt) {
+  const int m = threadIdx.x;
+  if (m < SS_MAXLEV) {
+    lt.off[m] = K.loff[m];
+    lt.lw[m] = K.lw[m];
+    lt.lh[m] = K.lh[m];
+    lt.ip[m] = K.inv_pow2[m];
+  }
+}
+
+__device__ __forceinline__ float vbound(const ViewK& K, const VTab& lt, int m, int cx, int cy) {
+  const float* base = m == 0 ? K.bnd : K.bmm + lt.off[m];
+  return base[__umul24((unsigned)cy, (unsigned)lt.lw[m]) + (unsigned)cx];
 }
 
 // Texel coordinates of the ray point at t.
@@ -190,8 +208,8 @@ __device__ VHit view_dense(const ViewK& K, const VRay<SPHERE>& r, float t0, floa
 
 // Hierarchical mode: front-to-back walk over the tap-bound pyramid.
 template <bool SPHERE>
-__device__ VHit view_hier(const ViewK& K, const VRay<SPHERE>& r, float t0, float t1,
-                          float eyen) {
+__device__ VHit view_hier(const ViewK& K, const VTab& lt, const VRay<SPHERE>& r, float t0,
+                          float t1, float eyen) {
   VHit h{-1, 0, 0};
   float t = t0;
   // start three levels below the top (cells of 1/8 of the tile): every ray
@@ -201,8 +219,8 @@ __device__ VHit view_hier(const ViewK& K, const VRay<SPHERE>& r, float t0, float
   if (m < K.L - 1) {
     float qx, qy;
     vq<SPHERE>(K, r, t, qx, qy);
-    cx = min(max((int)floorf(qx * K.inv_pow2[m]), 0), K.lw[m] - 1);
-    cy = min(max((int)floorf(qy * K.inv_pow2[m]), 0), K.lh[m] - 1);
+    cx = min(max((int)floorf(qx * lt.ip[m]), 0), lt.lw[m] - 1);
+    cy = min(max((int)floorf(qy * lt.ip[m]), 0), lt.lh[m] - 1);
   }
   for (int it = 0; it < K.max_iter; ++it) {
     h.cells++;
@@ -216,7 +234,7 @@ __device__ VHit view_hier(const ViewK& K, const VRay<SPHERE>& r, float t0, float
     const float tm = fminf(fmaxf(r.t_hmin, t), tb);
     const float Hmin = vH<SPHERE>(K, r, tm);
     const float margin = fmaf(K.m_rel, eyen + tb, K.m_abs);
-    const float Bm = vbound(K, m, cx, cy) + margin;
+    const float Bm = vbound(K, lt, m, cx, cy) + margin;
     bool pass = Hmin > Bm;
     if (!pass) {
       // the ray's height is convex in t, so its tangent at t is a lower bound:
@@ -233,9 +251,9 @@ __device__ VHit view_hier(const ViewK& K, const VRay<SPHERE>& r, float t0, float
       float qx, qy;
       vq<SPHERE>(K, r, t, qx, qy);
       --m;
-      const int kx = (int)floorf(qx * K.inv_pow2[m]), ky = (int)floorf(qy * K.inv_pow2[m]);
-      cx = min(max(kx, 2 * cx), min(2 * cx + 1, K.lw[m] - 1));
-      cy = min(max(ky, 2 * cy), min(2 * cy + 1, K.lh[m] - 1));
+      const int kx = (int)floorf(qx * lt.ip[m]), ky = (int)floorf(qy * lt.ip[m]);
+      cx = min(max(kx, 2 * cx), min(2 * cx + 1, lt.lw[m] - 1));
+      cy = min(max(ky, 2 * cy), min(2 * cy + 1, lt.lh[m] - 1));
       continue;
     }
     if (!pass) {
@@ -254,7 +272,7 @@ __device__ VHit view_hier(const ViewK& K, const VRay<SPHERE>& r, float t0, float
     const bool stx = tx <= ty, sty = ty <= tx;
     if (stx) cx += r.sgx;
     if (sty) cy += r.sgy;
-    if (cx < 0 || cy < 0 || cx >= K.lw[m] || cy >= K.lh[m]) return h;
+    if (cx < 0 || cy < 0 || cx >= lt.lw[m] || cy >= lt.lh[m]) return h;
     // one level up when the step left the parent cell
     const bool up = m < K.L - 1 && ((stx && ((cx & 1) == (r.sgx > 0 ? 0 : 1))) ||
                                     (sty && ((cy & 1) == (r.sgy > 0 ? 0 : 1))));
@@ -272,6 +290,11 @@ template <bool SPHERE, int MODE>
 __global__ __launch_bounds__(256) void view_kernel(ViewK K, float* __restrict__ out_t,
                                                    float2* __restrict__ out_xy,
                                                    int2* __restrict__ out_steps) {
+  __shared__ VTab lt;
+  if (MODE == SS_VIEW_HIER) {
+    vtab_fill(K, lt);
+    __syncthreads();
+  }
   // a wavefront covers an 8 x 8 pixel tile, a workgroup 16 x 16 pixels
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int bx = blockIdx.x % K.nbx, by = blockIdx.x / K.nbx;
@@ -314,7 +337,7 @@ __global__ __launch_bounds__(256) void view_kernel(ViewK K, float* __restrict__ 
     t_lo = fmaxf(lx, ly);
     t_hi = fminf(fminf(hx, hy), K.far);
     // the shell below the highest terrain (the pyramid's top entry)
-    const float hs = vbound(K, K.L - 1, 0, 0);
+    const float hs = (K.L == 1 ? K.bnd : K.bmm + K.loff[K.L - 1])[0];
     if (SPHERE) {
       const float b = fmaf(K.R, r.vz, fmaf(r.ex, r.vx, fmaf(r.ey, r.vy, r.ez * r.vz)));
       const float e2 = fmaf(r.ex, r.ex, fmaf(r.ey, r.ey, r.ez * r.ez));
@@ -348,7 +371,7 @@ __global__ __launch_bounds__(256) void view_kernel(ViewK K, float* __restrict__ 
     if (t_lo < t_hi) {
       const float eyen = sqrtf(fmaf(r.ex, r.ex, fmaf(r.ey, r.ey, r.ez * r.ez)));
       h = MODE == SS_VIEW_DENSE ? view_dense<SPHERE>(K, r, t_lo, t_hi)
-                                : view_hier<SPHERE>(K, r, t_lo, t_hi, eyen);
+                                : view_hier<SPHERE>(K, lt, r, t_lo, t_hi, eyen);
     }
   }
   const unsigned k = __umul24((unsigned)py, (unsigned)K.img_w) + (unsigned)px;
