@@ -190,3 +190,26 @@ def test_view_descent_trajectory(ss, diff, alt_km, hfov):
                               label=f"{alt_km} km")
     print(stats)
     assert stats["exact"] > 500
+
+
+def test_view_polar_tile(ss):
+    """The 16384^2 polar tile (2 m/texel, 15 pyramid levels, 33 km across): a camera 20 km up
+    looking across it; walk equals dense march, and sampled pixels match the oracle."""
+    h = synth.dem_for("polar", device="cuda")
+    from synth.configs import look_at
+    cam = look_at((-12e3, -9e3, 20e3), (2e3, 1e3, 0.0), 50.0, 160, 90, 1.0)
+    print("view polar", flush=True)
+    c = ss.Camera(**cam)
+    t, xy = ss.view_cast(h, 2.0, c, R)
+    td, xyd = ss.view_cast(h, 2.0, ss.Camera(**cam, mode=ss.SS_VIEW_DENSE), R)
+    torch.cuda.synchronize()
+    t, xy, td, xyd = (a.cpu().numpy() for a in (t, xy, td, xyd))
+    assert np.array_equal(bits(t), bits(td)) and np.array_equal(bits(xy), bits(xyd))
+    hn = h.cpu().numpy()
+    del h
+    rng = np.random.default_rng(9)
+    pix = np.stack([rng.integers(0, 160, 600), rng.integers(0, 90, 600)], axis=1)
+    stats = view_parity.check(hn, R, 2.0, oracle.Camera(**cam), t, xy, pixels=pix,
+                              label="polar")
+    print(stats)
+    assert stats["exact"] > 300
