@@ -417,7 +417,8 @@ def leg_frame(ss, reps=10):
     """Whole frames as Sec. 4 and 6.3 run them, on the 2048^2 tile (10 m/texel; the
     paper's stitched fields are 1024-2048 texels): view rays from a camera 8 km up
     heading across the tile (25 degrees down, 60 degree field of view), then one
-    shadow ray from every visible point, in each shadow mode.  Per image size: view
+    shadow ray from every visible point (shaded in 8 x 8 pixel tiles), in each shadow mode.
+    Per image size: view
     rays by the pyramid walk and by the dense march (identical output), grid samples
     and pyramid cells per pixel, shadow rays per mode, and the frame time and rate
     (view walk + shadows).  Terrain set-up (max-mip, tap-bound pyramid) runs once per
@@ -449,13 +450,12 @@ def leg_frame(ss, reps=10):
         cd = ss.Camera(**cam, mode=ss.SS_VIEW_DENSE)
         t = torch.empty((ph, pw), dtype=torch.float32, device=h.device)
         xy = torch.empty((ph, pw, 2), dtype=torch.float32, device=h.device)
-        s = torch.empty(ph * pw, dtype=torch.float32, device=h.device)
+        s = torch.empty((ph, pw), dtype=torch.float32, device=h.device)
         _, _, st = ss.view_cast(h, D, ch, R_MOON, bound, steps=True)
         _, _, sd = ss.view_cast(h, D, cd, R_MOON, bound, steps=True)
         vh = min(_timed(lambda: ss.view_cast(h, D, ch, R_MOON, bound, out_t=t, out_xy=xy), reps))
         vd = min(_timed(lambda: ss.view_cast(h, D, cd, R_MOON, bound, out_t=t, out_xy=xy), reps))
         ss.view_cast(h, D, ch, R_MOON, bound, out_t=t, out_xy=xy)
-        pts = xy.view(-1, 2)
         res = {"view_walk_ms": vh, "view_dense_ms": vd,
                "visible_frac": float(torch.isfinite(t).float().mean()),
                "walk_samples_per_pixel": float(st[..., 0].float().mean()),
@@ -464,9 +464,9 @@ def leg_frame(ss, reps=10):
         res["steps_ratio_dense_over_walk"] = res["dense_samples_per_pixel"] / (
             res["walk_samples_per_pixel"] + res["walk_cells_per_pixel"])
         for name, p in modes.items():
-            ss.shadow_points(h, D, e, a, pts, r, p, mm, out=s, bound=bound)
-            ms = min(_timed(lambda: ss.shadow_points(h, D, e, a, pts, r, p, mm, out=s,
-                                                     bound=bound), reps))
+            ss.shadow_points_image(h, D, e, a, xy, r, p, mm, out=s, bound=bound)
+            ms = min(_timed(lambda: ss.shadow_points_image(h, D, e, a, xy, r, p, mm, out=s,
+                                                           bound=bound), reps))
             res[f"shadow_{name}_ms"] = ms
             res[f"frame_{name}_ms"] = vh + ms
             res[f"frame_{name}_hz"] = 1e3 / (vh + ms)

@@ -252,6 +252,14 @@ int32_t ss_view_cast(const ss_tile* tile, double body_radius_m, const ss_camera*
 int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                          const float* d_xy, int64_t n, float* d_shadow, void* stream);
 
+/* ss_shadow_points over an image of points: d_xy is [height][width] float2
+ * (ss_view_cast's output), d_shadow [height][width]; width, height 1..16384.
+ * The values are ss_shadow_points' on the same points bit for bit; work is
+ * grouped in 8 x 8 pixel tiles, whose hits are neighbours on the terrain. */
+int32_t ss_shadow_points_image(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                               const float* d_xy, int32_t width, int32_t height, float* d_shadow,
+                               void* stream);
+
 /* Forward that also records, for every ray, the index n of its deciding
  * sample (the one whose clearance gave s): t = delta/2 + n * step with
  * step = delta/2, or the uniform step in SS_MODE_UNIFORM; -1 when no sample

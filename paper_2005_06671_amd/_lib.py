@@ -92,6 +92,9 @@ SIGNATURES = {
     "ss_batched_plan_destroy": (C.c_int32, [C.c_void_p]),
     "ss_shadow_points": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_shadow_points_image": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
+                                           C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                           C.c_void_p]),
     "ss_view_cast": (C.c_int32, [C.POINTER(SSTile), C.c_double, C.POINTER(SSCamera), C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
     "ss_resample": (C.c_int32, [C.c_void_p, C.POINTER(SSFrame), C.c_void_p, C.POINTER(SSFrame),

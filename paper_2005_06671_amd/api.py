@@ -357,9 +357,8 @@ def frame(h: torch.Tensor, texel_m: float, cam: Camera, elev: float, azim: float
     if bound is None:
         bound = bound_build(h)
     t, xy = view_cast(h, texel_m, cam, params.radius_m, bound)
-    s = shadow_points(h, texel_m, elev, azim, xy.view(-1, 2), ang_radius, params, mm,
-                      bound=bound)
-    return s.view(t.shape), t, xy
+    s = shadow_points_image(h, texel_m, elev, azim, xy, ang_radius, params, mm, bound=bound)
+    return s, t, xy
 
 
 @dataclass
@@ -404,6 +403,33 @@ def stitch(sources, fd: Frame, radius_m: float = 1737400.0, out: torch.Tensor | 
         out = torch.full((fd.rows, fd.width), float("nan"), dtype=torch.float32, device=dev)
     for h, f in sources:
         resample(h, f, out, fd, radius_m)
+    return out
+
+
+def shadow_points_image(h: torch.Tensor, texel_m: float, elev: float, azim: float,
+                        xy: torch.Tensor, ang_radius: float = SUN_RADIUS_RAD,
+                        params: Params | None = None, mm: torch.Tensor | None = None,
+                        out: torch.Tensor | None = None,
+                        bound: torch.Tensor | None = None) -> torch.Tensor:
+    """s at an image of surface points xy [H, W, 2] (float32 CUDA, as view_cast returns it):
+    shadow_points' values, shaded in 8 x 8 pixel tiles.  Returns [H, W]."""
+    _dev_f32_2d(h)
+    if (not isinstance(xy, torch.Tensor) or xy.dim() != 3 or xy.shape[2] != 2 or not xy.is_cuda
+            or xy.dtype != torch.float32 or not xy.is_contiguous()):
+        raise ValueError("xy must be a contiguous float32 CUDA tensor [H, W, 2]")
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
+    H, W = int(xy.shape[0]), int(xy.shape[1])
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=h.device)
+    t = _tile(h, mm, texel_m, bound)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_points_image",
+            L.lib().ss_shadow_points_image(C.byref(t), C.byref(s), C.byref(p), xy.data_ptr(), W, H,
+                                           out.data_ptr(), _stream(h.device)))
     return out
 
 

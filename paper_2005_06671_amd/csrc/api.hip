@@ -350,7 +350,26 @@ extern "C" int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun,
   if ((reinterpret_cast<uintptr_t>(d_xy) & 7) != 0) return SS_ERR_INVALID_ARG;
   TileK K;
   if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
-  SS_HIP(launch_points(K, rp.sphere, rp.mode, d_xy, n, d_shadow, (hipStream_t)stream));
+  SS_HIP(launch_points(K, rp.sphere, rp.mode, d_xy, n, 0, d_shadow, (hipStream_t)stream));
+  return SS_OK;
+}
+
+extern "C" int32_t ss_shadow_points_image(const ss_tile* tile, const ss_sun* sun,
+                                          const ss_params* params, const float* d_xy,
+                                          int32_t width, int32_t height, float* d_shadow,
+                                          void* stream) {
+  Resolved rp;
+  int32_t rc = resolve_params(params, &rp);
+  if (rc) return rc;
+  if ((rc = check_tile(tile, rp.mode))) return rc;
+  if ((rc = check_sun(sun))) return rc;
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return SS_ERR_INVALID_ARG;
+  if (!d_xy || !d_shadow || tile->width == 0 || tile->rows == 0) return SS_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(d_xy) & 7) != 0) return SS_ERR_INVALID_ARG;
+  TileK K;
+  if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
+  SS_HIP(launch_points(K, rp.sphere, rp.mode, d_xy, (long long)width * height, width, d_shadow,
+                       (hipStream_t)stream));
   return SS_OK;
 }
 

@@ -20,9 +20,10 @@ hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, b
                           float* out, unsigned long long* counter, int* sample,
                           hipStream_t stream);
 
-// Shadow rays from n surface points (float2 continuous texel coordinates).
+// Shadow rays from n surface points (float2 continuous texel coordinates);
+// img_w > 0: the points are an image of img_w columns, shaded in pixel tiles.
 hipError_t launch_points(const TileK& T, bool sphere, int mode, const float* xy, long long n,
-                         float* out, hipStream_t stream);
+                         int img_w, float* out, hipStream_t stream);
 
 // sample != nullptr: take the deciding samples from there instead of replaying.
 hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,

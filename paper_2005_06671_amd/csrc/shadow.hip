@@ -282,20 +282,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
 // Shadow rays from arbitrary surface points: point k at continuous texel
 // coordinates xy[k] (clamped to the tile), on the bilinear terrain there.
 template <bool SPHERE, int MODE>
-__global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __restrict__ xy,
-                                                     long long n, float* __restrict__ out) {
-  __shared__ int tab[SS_MAXLEV];
-  if (MODE == SS_MODE_EXACT) {
-    bound_tab_fill(T, tab);
-    __syncthreads();
-  }
-  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  const float2 q = xy[k];
-  if (q.x != q.x || q.y != q.y) {  // a view ray's miss: nothing to shade
-    out[k] = NAN;
-    return;
-  }
+__device__ __forceinline__ float shade_point(const TileK& T, float2 q, const int* tab) {
+  if (q.x != q.x || q.y != q.y) return NAN;  // a view ray's miss: nothing to shade
   const float qx = fminf(fmaxf(q.x, 0.0f), (float)T.W), qy = fminf(fmaxf(q.y, 0.0f), (float)T.H);
   const int i = min((int)floorf(qx), T.W - 1), j = min((int)floorf(qy), T.H - 1);
   // heights relative to the texel's own, the origin dz above it
@@ -304,34 +292,72 @@ __global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __re
   ray_init(T, i, j, ref, r, qx - ((float)i + 0.5f), qy - ((float)j + 0.5f),
            terrain_above(T, qx, qy, ref));
   unsigned n_lb = 0, n_smp = 0;
-  out[k] = disc_fraction(trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab).alpha, T);
+  return disc_fraction(trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab).alpha, T);
+}
+
+// IMAGE: the points form an image [n / img_w][img_w] and a wavefront takes an
+// 8 x 8 pixel tile (a workgroup 16 x 16): neighbouring pixels' hits are
+// neighbours on the terrain, so their shadow rays walk the same cells (a row
+// of 64 pixels spreads them out).  Otherwise lane k takes point k.
+template <bool SPHERE, int MODE, bool IMAGE>
+__global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __restrict__ xy,
+                                                     long long n, int img_w, int nbx,
+                                                     float* __restrict__ out) {
+  __shared__ int tab[SS_MAXLEV];
+  if (MODE == SS_MODE_EXACT) {
+    bound_tab_fill(T, tab);
+    __syncthreads();
+  }
+  long long k;
+  if (IMAGE) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int bx = (int)(blockIdx.x % (unsigned)nbx), by = (int)(blockIdx.x / (unsigned)nbx);
+    const int px = bx * 16 + (wv & 1) * 8 + (lane & 7);
+    const int py = by * 16 + (wv >> 1) * 8 + (lane >> 3);
+    if (px >= img_w) return;
+    k = (long long)py * img_w + px;  // >= n for rows past the image
+  } else {
+    k = (long long)blockIdx.x * 256 + threadIdx.x;
+  }
+  if (k >= n) return;
+  out[k] = shade_point<SPHERE, MODE>(T, xy[k], tab);
 }
 
 template <bool SPHERE, int MODE>
-static void points_launch(const TileK& T, const float* xy, long long n, float* out,
-                          hipStream_t stream) {
-  hipLaunchKernelGGL((points_kernel<SPHERE, MODE>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     stream, T, reinterpret_cast<const float2*>(xy), n, out);
+static void points_launch(const TileK& T, const float* xy, long long n, int img_w,
+                          float* out, hipStream_t stream) {
+  const float2* q = reinterpret_cast<const float2*>(xy);
+  if (img_w > 0) {
+    const int nbx = (img_w + 15) / 16;
+    const long long rows = n / img_w, nby = (rows + 15) / 16;
+    hipLaunchKernelGGL((points_kernel<SPHERE, MODE, true>), dim3((unsigned)(nbx * nby)),
+                       dim3(256), 0, stream, T, q, n, img_w, nbx, out);
+  } else {
+    hipLaunchKernelGGL((points_kernel<SPHERE, MODE, false>), dim3((unsigned)((n + 255) / 256)),
+                       dim3(256), 0, stream, T, q, n, 0, 1, out);
+  }
 }
 
 template <bool SPHERE>
-static void points_mode(const TileK& T, int mode, const float* xy, long long n, float* out,
-                        hipStream_t stream) {
+static void points_mode(const TileK& T, int mode, const float* xy, long long n, int img_w,
+                        float* out, hipStream_t stream) {
   switch (mode) {
-    case SS_MODE_EXACT: points_launch<SPHERE, SS_MODE_EXACT>(T, xy, n, out, stream); break;
-    case SS_MODE_POINT: points_launch<SPHERE, SS_MODE_POINT>(T, xy, n, out, stream); break;
-    case SS_MODE_UNIFORM: points_launch<SPHERE, SS_MODE_UNIFORM>(T, xy, n, out, stream); break;
-    default: points_launch<SPHERE, SS_MODE_DP>(T, xy, n, out, stream); break;
+    case SS_MODE_EXACT: points_launch<SPHERE, SS_MODE_EXACT>(T, xy, n, img_w, out, stream); break;
+    case SS_MODE_POINT: points_launch<SPHERE, SS_MODE_POINT>(T, xy, n, img_w, out, stream); break;
+    case SS_MODE_UNIFORM:
+      points_launch<SPHERE, SS_MODE_UNIFORM>(T, xy, n, img_w, out, stream);
+      break;
+    default: points_launch<SPHERE, SS_MODE_DP>(T, xy, n, img_w, out, stream); break;
   }
 }
 
 hipError_t launch_points(const TileK& T, bool sphere, int mode, const float* xy, long long n,
-                         float* out, hipStream_t stream) {
+                         int img_w, float* out, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   if (sphere)
-    points_mode<true>(T, mode, xy, n, out, stream);
+    points_mode<true>(T, mode, xy, n, img_w, out, stream);
   else
-    points_mode<false>(T, mode, xy, n, out, stream);
+    points_mode<false>(T, mode, xy, n, img_w, out, stream);
   return hipGetLastError();
 }
 

@@ -124,6 +124,11 @@ int main(void) {
   EXPECT(ss_shadow_points(&t, &sun, &p, FAKE(0x400000), -1, FAKE(0x500000), NULL) ==
          SS_ERR_INVALID_ARG);
 
+  EXPECT(ss_shadow_points_image(&t, &sun, &p, FAKE(0x400000), 0, 8, FAKE(0x500000), NULL) ==
+         SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_points_image(&t, &sun, &p, FAKE(0x400004), 8, 8, FAKE(0x500000), NULL) ==
+         SS_ERR_INVALID_ARG);
+
   /* batched */
   ss_tile tiles[2] = {tile(64, 64), tile(128, 32)};
   ss_sun suns[2] = {sun, sun};

@@ -282,3 +282,13 @@ def test_resample_validation(L):
     # overlapping buffers (64 x 32 floats = 8 KiB)
     assert call(d=src + 4096) == L.SS_ERR_INVALID_ARG
     assert call(s=dst + 8188) == L.SS_ERR_INVALID_ARG
+
+
+def test_points_image_validation(L):
+    lib = L.lib()
+    t, s, p = good(L)
+    f = lambda xy=0x400000, w=64, h=32, out=0x500000: lib.ss_shadow_points_image(  # noqa: E731
+        C.byref(t), C.byref(s), C.byref(p), xy, w, h, out, None)
+    for args in [dict(w=0), dict(h=0), dict(w=16385), dict(xy=None), dict(out=None),
+                 dict(xy=0x400004)]:
+        assert f(**args) == L.SS_ERR_INVALID_ARG, args

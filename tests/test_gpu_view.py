@@ -213,3 +213,21 @@ def test_view_polar_tile(ss):
                               label="polar")
     print(stats)
     assert stats["exact"] > 300
+
+
+@pytest.mark.parametrize("shape", [(1080, 1920), (23, 37), (16, 16)])
+def test_points_image_equals_list(ss, diff, shape):
+    """ss_shadow_points_image gives ss_shadow_points' values bit for bit (pixel-tiled work,
+    ragged images included); misses stay NaN."""
+    H, W = shape
+    cam = view_scene("flyover", W, H, 2048, 2048, 10.0)
+    hd = torch.from_numpy(diff).cuda()
+    t, xy = ss.view_cast(hd, 10.0, ss.Camera(**cam), R)
+    e, a, r = synth.sun_list("diff")[0]
+    for mode in (ss.SS_MODE_DP, ss.SS_MODE_POINT, ss.SS_MODE_EXACT):
+        p = ss.Params(radius_m=R, max_len_m=30000.0, mode=mode)
+        si = ss.shadow_points_image(hd, 10.0, e, a, xy, r, p)
+        sl = ss.shadow_points(hd, 10.0, e, a, xy.view(-1, 2), r, p)
+        torch.cuda.synchronize()
+        assert torch.equal(si.view(-1).view(torch.int32), sl.view(torch.int32)), mode
+    assert torch.equal(torch.isnan(si), ~torch.isfinite(t))
