@@ -246,11 +246,29 @@ int32_t ss_view_cast(const ss_tile* tile, double body_radius_m, const ss_camera*
  * each ray starts on the bilinear terrain there (Sec. 3.4's sampling) and runs
  * the chosen mode exactly as a texel-centre ray does; d_shadow[n] receives s.
  * Points outside the tile are clamped to its edge; a point with a NaN
- * coordinate (a view ray's miss) gets s = NaN.  The ray window is ignored.  Texel centres (i + 1/2, j + 1/2) give ss_shadow_cast's values.
- * This is the call a view-ray caster feeds (Sec. 4: shadows at the visible
- * surface points of a frame). */
+ * coordinate (a view ray's miss) gets s = NaN.  The ray window is ignored.
+ * Texel centres (i + 1/2, j + 1/2) give ss_shadow_cast's values.  n is at most
+ * SS_MAX_POINTS.  This is the call a view-ray caster feeds (Sec. 4: shadows at
+ * the visible surface points of a frame). */
+#define SS_MAX_POINTS (1LL << 36)
+
 int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                          const float* d_xy, int64_t n, float* d_shadow, void* stream);
+
+/* Adjoint of ss_shadow_points (every mode) with the points held fixed:
+ * ACCUMULATES (+=) dL/dh into d_grad_height [rows][width] and dL/d(elev, azim)
+ * into d_grad_sun[2] (FP64), given dL/ds in d_grad_shadow[n].  A ray's origin
+ * sits on the bilinear terrain at its point, so dL/d(origin height) goes to
+ * the four texels that bilinear sample reads; the rest is the texel-centre
+ * adjoint.  width = 0: a list of points; width > 0: an image of that many
+ * columns (n a multiple of it, at most 16384 rows), worked in 8 x 8 pixel
+ * tiles.  NaN points and zero upstream gradients contribute nothing.
+ * d_grad_sun must be 8-byte aligned.  Accumulation uses atomics, so the
+ * summation order is not fixed. */
+int32_t ss_shadow_points_backward(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
+                                  const float* d_xy, int64_t n, int32_t width,
+                                  const float* d_grad_shadow, float* d_grad_height,
+                                  double* d_grad_sun, void* stream);
 
 /* ss_shadow_points over an image of points: d_xy is [height][width] float2
  * (ss_view_cast's output), d_shadow [height][width]; width, height 1..16384.

@@ -25,22 +25,47 @@ import torch
 F64 = torch.float64
 
 
+def _bilinear(h: torch.Tensor, qx: torch.Tensor, qy: torch.Tensor) -> torch.Tensor:
+    """Bilinear height over texel centres, taps clamped to the tile (Sec. 3.4 sampling)."""
+    rows, width = h.shape
+    x, y = qx - 0.5, qy - 0.5
+    x0, y0 = torch.floor(x.detach()), torch.floor(y.detach())
+    fx, fy = x - x0, y - y0
+    i0 = x0.long().clamp(0, width - 1)
+    i1 = (x0.long() + 1).clamp(0, width - 1)
+    j0 = y0.long().clamp(0, rows - 1)
+    j1 = (y0.long() + 1).clamp(0, rows - 1)
+    return (1 - fy) * ((1 - fx) * h[j0, i0] + fx * h[j0, i1]) + fy * ((1 - fx) * h[j1, i0] + fx * h[j1, i1])
+
+
 def shadow_on_branch(h: torch.Tensor, elev: torch.Tensor, azim: torch.Tensor, p, trace,
-                     rays=None) -> torch.Tensor:
+                     rays=None, points=None) -> torch.Tensor:
     """s for the given rays along the oracle's branch, differentiable in h, elev, azim.
 
     h: float64 [rows, width] (may require grad); elev, azim: 0-d float64 tensors.
     p: oracle.Params (its elev/azim are ignored in favour of the tensors).
     trace: oracle trace records for the same rays (structured numpy array).
     rays: linear texel indices, or None for every texel in order.
+    points: instead of texel centres, rays from these surface points ([n, 2] continuous
+    texel coordinates); the origin height is then the bilinear terrain there, so it
+    depends on the four texels around the point.
     """
     rows, width = h.shape
     tr = np.asarray(trace).reshape(-1)
-    lin = np.arange(rows * width) if rays is None else np.asarray(rays).reshape(-1)
     seg = torch.as_tensor(tr["seg"].astype(np.int64))
     n = torch.as_tensor(tr["n"].astype(np.float64), dtype=F64)
-    i = torch.as_tensor(lin % width)
-    j = torch.as_tensor(lin // width)
+    if points is None:
+        lin = np.arange(rows * width) if rays is None else np.asarray(rays).reshape(-1)
+        i = torch.as_tensor(lin % width)
+        j = torch.as_tensor(lin // width)
+        ox = torch.zeros(len(lin), dtype=F64)
+        oy = torch.zeros(len(lin), dtype=F64)
+    else:
+        pts = np.asarray(points, dtype=np.float64).reshape(-1, 2)
+        i = torch.as_tensor(np.floor(pts[:, 0]).astype(np.int64))
+        j = torch.as_tensor(np.floor(pts[:, 1]).astype(np.int64))
+        ox = torch.as_tensor(pts[:, 0] - (np.floor(pts[:, 0]) + 0.5))
+        oy = torch.as_tensor(pts[:, 1] - (np.floor(pts[:, 1]) + 0.5))
     lit = seg == -2
     D = float(p.texel_m)
     planar = math.isinf(p.radius_m)
@@ -51,9 +76,12 @@ def shadow_on_branch(h: torch.Tensor, elev: torch.Tensor, azim: torch.Tensor, p,
     delta = D / ce
     t = 0.5 * delta + n * (0.5 * delta)
 
-    X = (i.to(F64) + 0.5 - 0.5 * width) * D
-    Y = (j.to(F64) + 0.5 - 0.5 * rows) * D
-    hp = h[j, i]
+    X = (i.to(F64) + 0.5 + ox - 0.5 * width) * D
+    Y = (j.to(F64) + 0.5 + oy - 0.5 * rows) * D
+    if points is None:
+        hp = h[j, i]
+    else:
+        hp = _bilinear(h, i.to(F64) + 0.5 + ox, j.to(F64) + 0.5 + oy)
     if planar:
         nrm = torch.stack([torch.zeros_like(X), torch.zeros_like(X), torch.ones_like(X)])
         P = torch.stack([X + t * L[0], Y + t * L[1], hp + t * L[2]])
@@ -107,12 +135,12 @@ def shadow_on_branch(h: torch.Tensor, elev: torch.Tensor, azim: torch.Tensor, p,
     return torch.where(lit, torch.ones_like(out), out)
 
 
-def reference_gradient(h_np: np.ndarray, p, trace, grad_s: np.ndarray, rays=None):
+def reference_gradient(h_np: np.ndarray, p, trace, grad_s: np.ndarray, rays=None, points=None):
     """(dL/dh [rows,width] float64, dL/delev, dL/dazim) for L = sum(grad_s * s)."""
     h = torch.tensor(np.asarray(h_np, dtype=np.float64), dtype=F64, requires_grad=True)
     e = torch.tensor(float(p.elev), dtype=F64, requires_grad=True)
     a = torch.tensor(float(p.azim), dtype=F64, requires_grad=True)
-    s = shadow_on_branch(h, e, a, p, trace, rays)
+    s = shadow_on_branch(h, e, a, p, trace, rays, points)
     g = torch.as_tensor(np.asarray(grad_s, dtype=np.float64).reshape(-1))
     (s * g).sum().backward()
     return h.grad.numpy(), float(e.grad), float(a.grad), s.detach().numpy()

@@ -9,6 +9,7 @@ from .api import (  # noqa: F401
     bound_build, bound_floats, bound_level_offset, bound_unpack,
     shadow_cast_save, shadow_cast_backward_saved, probe_gather, shadow_points,
     Camera, view_cast, frame, Frame, resample, stitch, shadow_points_image,
+    shadow_points_backward, ShadowPoints, shadow_at,
 )
 from ._lib import lib, SoftShadowError, RAY_TILES, SS_MODE_DP, SS_MODE_UNIFORM  # noqa: F401
 from ._lib import SS_MODE_EXACT, SS_MODE_POINT, SS_VIEW_HIER, SS_VIEW_DENSE  # noqa: F401

@@ -92,6 +92,10 @@ SIGNATURES = {
     "ss_batched_plan_destroy": (C.c_int32, [C.c_void_p]),
     "ss_shadow_points": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ss_shadow_points_backward": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun),
+                                              C.POINTER(SSParams), C.c_void_p, C.c_int64,
+                                              C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_void_p]),
     "ss_shadow_points_image": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
                                            C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                            C.c_void_p]),

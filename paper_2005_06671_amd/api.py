@@ -494,6 +494,88 @@ def shadow(h, elev, azim, texel_m, ang_radius=SUN_RADIUS_RAD, params: Params | N
     return ShadowCast.apply(h, elev, azim, texel_m, ang_radius, params, window)
 
 
+def shadow_points_backward(h: torch.Tensor, texel_m: float, elev: float, azim: float,
+                           xy: torch.Tensor, grad_s: torch.Tensor,
+                           ang_radius: float = SUN_RADIUS_RAD, params: Params | None = None,
+                           mm: torch.Tensor | None = None, bound: torch.Tensor | None = None,
+                           grad_h: torch.Tensor | None = None,
+                           grad_sun: torch.Tensor | None = None):
+    """Adjoint of shadow_points / shadow_points_image with the points held fixed
+    (ss_shadow_points_backward).  xy: [n, 2] or an image [H, W, 2]; grad_s: n or [H, W]
+    values.  Returns (dL/dh float32 [rows, width], dL/d(elev, azim) float64 [2]),
+    accumulated into grad_h / grad_sun when given."""
+    _dev_f32_2d(h)
+    if (not isinstance(xy, torch.Tensor) or xy.dim() not in (2, 3) or xy.shape[-1] != 2
+            or not xy.is_cuda or xy.dtype != torch.float32 or not xy.is_contiguous()):
+        raise ValueError("xy must be a contiguous float32 CUDA tensor [n, 2] or [H, W, 2]")
+    n = xy.numel() // 2
+    width = int(xy.shape[1]) if xy.dim() == 3 else 0
+    g = grad_s.contiguous()
+    if g.numel() != n or g.dtype != torch.float32 or not g.is_cuda:
+        raise ValueError("grad_s must be float32 CUDA with one value per point")
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
+    if grad_h is None:
+        grad_h = torch.zeros_like(h)
+    if grad_sun is None:
+        grad_sun = torch.zeros(2, dtype=torch.float64, device=h.device)
+    t = _tile(h, mm, texel_m, bound)
+    s = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_points_backward",
+            L.lib().ss_shadow_points_backward(C.byref(t), C.byref(s), C.byref(p), xy.data_ptr(), n,
+                                              width, g.data_ptr(), grad_h.data_ptr(),
+                                              grad_sun.data_ptr(), _stream(h.device)))
+    return grad_h, grad_sun
+
+
+class ShadowPoints(torch.autograd.Function):
+    """s at fixed surface points (a frame's view hits), differentiable in the heights and the
+    sun direction: the forward is shadow_points (or shadow_points_image for [H, W, 2] points),
+    the backward the points adjoint kernel.  The points themselves get no gradient."""
+
+    @staticmethod
+    def forward(ctx, h, elev, azim, xy, texel_m, ang_radius, params):
+        e = float(elev)
+        a = float(azim)
+        hd = h.detach().contiguous()
+        mm = maxmip(hd)
+        bound = _bound_for(hd, params, None)
+        if xy.dim() == 3:
+            s = shadow_points_image(hd, texel_m, e, a, xy, ang_radius, params, mm, bound=bound)
+        else:
+            s = shadow_points(hd, texel_m, e, a, xy, ang_radius, params, mm, bound=bound)
+        ctx.save_for_backward(hd, mm, bound if bound is not None else hd.new_empty(0), xy)
+        ctx.has_bound = bound is not None
+        ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim)
+        return s
+
+    @staticmethod
+    def backward(ctx, grad_s):
+        hd, mm, bound, xy = ctx.saved_tensors
+        texel_m, e, a, ang_radius, params, elev, azim = ctx.cfg
+        g = torch.nan_to_num(grad_s.contiguous(), nan=0.0)
+        gh, gsun = shadow_points_backward(hd, texel_m, e, a, xy, g, ang_radius, params, mm=mm,
+                                          bound=bound if ctx.has_bound else None)
+        ge = gsun[0].to(elev.device) if isinstance(elev, torch.Tensor) else None
+        ga = gsun[1].to(azim.device) if isinstance(azim, torch.Tensor) else None
+        return gh, ge, ga, None, None, None, None
+
+
+def shadow_at(h, elev, azim, xy, texel_m, ang_radius=SUN_RADIUS_RAD,
+              params: Params | None = None):
+    """Differentiable shadow factor at fixed surface points xy ([n, 2] or a frame's [H, W, 2]
+    view hits; NaN points give NaN and no gradient)."""
+    params = params or Params()
+    if not isinstance(elev, torch.Tensor):
+        elev = torch.tensor(float(elev), dtype=torch.float64)
+    if not isinstance(azim, torch.Tensor):
+        azim = torch.tensor(float(azim), dtype=torch.float64)
+    return ShadowPoints.apply(h, elev, azim, xy, texel_m, ang_radius, params)
+
+
 # ---------------------------------------------------------------------------
 # Batched form
 # ---------------------------------------------------------------------------

@@ -330,6 +330,7 @@ static int32_t backward_common(const ss_tile* tile, const ss_sun* sun, const ss_
   if ((rc = check_sun(sun))) return rc;
   if (tile->width == 0 || tile->rows == 0) return SS_OK;
   if (!d_grad_shadow || !d_grad_height || !d_grad_sun) return SS_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(d_grad_sun) & 7) != 0) return SS_ERR_INVALID_ARG;
   TileK K;
   if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
   SS_HIP(launch_adjoint(K, rp.sphere, rp.mode, sun->elev_rad, sun->azim_rad, d_grad_shadow,
@@ -345,12 +346,36 @@ extern "C" int32_t ss_shadow_points(const ss_tile* tile, const ss_sun* sun,
   if (rc) return rc;
   if ((rc = check_tile(tile, rp.mode))) return rc;
   if ((rc = check_sun(sun))) return rc;
-  if (n < 0 || (n > 0 && (!d_xy || !d_shadow))) return SS_ERR_INVALID_ARG;
+  if (n < 0 || n > SS_MAX_POINTS || (n > 0 && (!d_xy || !d_shadow))) return SS_ERR_INVALID_ARG;
   if (n == 0 || tile->width == 0 || tile->rows == 0) return n == 0 ? SS_OK : SS_ERR_INVALID_ARG;
   if ((reinterpret_cast<uintptr_t>(d_xy) & 7) != 0) return SS_ERR_INVALID_ARG;
   TileK K;
   if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
   SS_HIP(launch_points(K, rp.sphere, rp.mode, d_xy, n, 0, d_shadow, (hipStream_t)stream));
+  return SS_OK;
+}
+
+extern "C" int32_t ss_shadow_points_backward(const ss_tile* tile, const ss_sun* sun,
+                                             const ss_params* params, const float* d_xy,
+                                             int64_t n, int32_t width,
+                                             const float* d_grad_shadow, float* d_grad_height,
+                                             double* d_grad_sun, void* stream) {
+  Resolved rp;
+  int32_t rc = resolve_params(params, &rp);
+  if (rc) return rc;
+  if ((rc = check_tile(tile, rp.mode))) return rc;
+  if ((rc = check_sun(sun))) return rc;
+  if (n < 0 || n > SS_MAX_POINTS || width < 0 || width > 16384) return SS_ERR_INVALID_ARG;
+  if (n == 0) return SS_OK;
+  if (width > 0 && (n % width != 0 || n / width > 16384)) return SS_ERR_INVALID_ARG;
+  if (!d_xy || !d_grad_shadow || !d_grad_height || !d_grad_sun) return SS_ERR_INVALID_ARG;
+  if (tile->width == 0 || tile->rows == 0) return SS_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(d_xy) & 7) != 0) return SS_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(d_grad_sun) & 7) != 0) return SS_ERR_INVALID_ARG;
+  TileK K;
+  if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
+  SS_HIP(launch_points_adjoint(K, rp.sphere, rp.mode, sun->elev_rad, sun->azim_rad, d_xy, n, width,
+                               d_grad_shadow, d_grad_height, d_grad_sun, (hipStream_t)stream));
   return SS_OK;
 }
 

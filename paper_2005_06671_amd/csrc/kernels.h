@@ -25,6 +25,11 @@ hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, b
 hipError_t launch_points(const TileK& T, bool sphere, int mode, const float* xy, long long n,
                          int img_w, float* out, hipStream_t stream);
 
+// Adjoint of launch_points (points held fixed), same work mapping.
+hipError_t launch_points_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
+                                 const float* xy, long long n, int img_w, const float* gs,
+                                 float* gh, double* gsun, hipStream_t stream);
+
 // sample != nullptr: take the deciding samples from there instead of replaying.
 hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
                           const float* gs, const int* sample, float* gh, double* gsun,

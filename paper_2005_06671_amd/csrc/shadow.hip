@@ -88,6 +88,119 @@ struct SunTrig {
   float se, ce, sa, ca, tan_e;
 };
 
+// The chain rule through one ray's deciding sample: adds to dL/dh at the
+// sample's four taps and to the sun gradient, and returns dL/d(origin height).
+// X, Y: the origin's plane position; r1 = 1 + (origin height) / R.
+template <bool SPHERE>
+__device__ __forceinline__ float adjoint_sample(const TileK& T, const SunTrig& st,
+                                                const Ray<SPHERE>& r, const RayResult& res,
+                                                float g, float X, float Y, float r1,
+                                                float* __restrict__ gh, double& ge, double& ga) {
+  const float dd = res.alpha * T.inv_rL;
+  if (!(res.valid && g != 0.0f && fabsf(dd) < 1.0f)) return 0.0f;
+  const float t = res.t, u = res.u;
+  const Sample s = sample_at(r, T, t, u);
+  const float dh = s.dh;
+  const float galpha = g * 2.0f * sqrtf(1.0f - dd * dd) * (0.318309886183791f * T.inv_rL);
+  float num, den, x = 0.0f, w = 1.0f;
+  if (SPHERE) {
+    x = t * r.invrho;
+    w = sqrtf(1.0f + x * (2.0f * r.sp + x));
+    num = dh * r.cp;
+    den = t * w - dh * (r.sp + x);
+  } else {
+    num = dh * r.cp;
+    den = t - dh * r.sp;
+  }
+  const float inv2 = 1.0f / (num * num + den * den);
+  const float a_n = galpha * den * inv2;
+  const float a_d = -galpha * num * inv2;
+  float a_dh, a_cp, a_sp, a_t, a_hp = 0.0f;
+  float a_Lx = 0.0f, a_Ly = 0.0f, a_Lz = 0.0f;
+  // bilinear taps
+  const int xa = min(max(s.x0, 0), T.W - 1), xb = min(max(s.x0 + 1, 0), T.W - 1);
+  const int ya = min(max(s.y0, 0), T.H - 1), yb = min(max(s.y0 + 1, 0), T.H - 1);
+  const float h00 = T.h[ya * T.W + xa], h10 = T.h[ya * T.W + xb];
+  const float h01 = T.h[yb * T.W + xa], h11 = T.h[yb * T.W + xb];
+  const float gxh = (1.0f - s.fy) * (h10 - h00) + s.fy * (h11 - h01);
+  const float gyh = (1.0f - s.fx) * (h01 - h00) + s.fx * (h11 - h10);
+  if (SPHERE) {
+    const float aa = X * T.invR, bb = Y * T.invR;
+    const float gg = sqrtf(1.0f + aa * aa + bb * bb);
+    const float G = gg / (r1 * T.texel);
+    a_dh = a_n * r.cp - a_d * (r.sp + x);
+    a_cp = a_n * dh;
+    a_t = a_d * w;
+    float a_w = a_d * t;
+    a_sp = -a_d * dh;
+    float a_x = -a_d * dh;
+    // dh = dH(t, rho, sp) - (hb - hp)
+    const float a_hb = -a_dh;
+    a_hp += a_dh;
+    const float spx = r.sp + x;
+    const float wm1 = x * (2.0f * r.sp + x) / (w + 1.0f);
+    a_t += a_dh * spx / w;
+    a_sp += a_dh * t / w;
+    float a_rho = a_dh * (wm1 - x * spx / w);
+    a_x += a_w * spx / w;
+    a_sp += a_w * x / w;
+    a_t += a_x * r.invrho;
+    a_rho -= a_x * x * r.invrho;
+    // texture position d = K u(t)
+    const float a_dx = a_hb * gxh, a_dy = a_hb * gyh;
+    const float omc = 1.0f - r.c * u;  // = 1 / (1 + c t)
+    const float k1 = omc * omc;
+    const float aK = a_dx * r.Kx + a_dy * r.Ky;
+    a_t += aK * k1;
+    a_rho -= aK * k1 * x;
+    a_Lx += a_dx * G * u;
+    a_Ly += a_dy * G * u;
+    a_Lz += -G * u * (a_dx * aa + a_dy * bb) - aK * k1 * t * t * (gg * T.invR / r1);
+    // s_p = (aa Lx + bb Ly + Lz)/g and c_p = sqrt(1 - s_p^2)
+    a_sp += -a_cp * r.sp / r.cp;
+    const float ig = 1.0f / gg;
+    a_Lx += a_sp * aa * ig;
+    a_Ly += a_sp * bb * ig;
+    a_Lz += a_sp * ig;
+    a_hp += a_rho;
+    // taps
+    atomicAdd(&gh[ya * T.W + xa], a_hb * (1.0f - s.fx) * (1.0f - s.fy));
+    atomicAdd(&gh[ya * T.W + xb], a_hb * s.fx * (1.0f - s.fy));
+    atomicAdd(&gh[yb * T.W + xa], a_hb * (1.0f - s.fx) * s.fy);
+    atomicAdd(&gh[yb * T.W + xb], a_hb * s.fx * s.fy);
+  } else {
+    a_dh = a_n * r.cp - a_d * r.sp;
+    a_cp = a_n * dh;
+    a_sp = -a_d * dh;
+    a_t = a_d;
+    a_t += a_dh * T.Lz;
+    a_Lz += a_dh * t;
+    const float a_hb = -a_dh;
+    a_hp += a_dh;
+    const float a_dx = a_hb * gxh, a_dy = a_hb * gyh;
+    const float it = 1.0f / T.texel;
+    a_t += (a_dx * T.Lx + a_dy * T.Ly) * it;
+    a_Lx += a_dx * t * it;
+    a_Ly += a_dy * t * it;
+    a_Lz += a_sp;
+    if (r.cp > 0.0f) {
+      a_Lx += a_cp * T.Lx / r.cp;
+      a_Ly += a_cp * T.Ly / r.cp;
+    }
+    atomicAdd(&gh[ya * T.W + xa], a_hb * (1.0f - s.fx) * (1.0f - s.fy));
+    atomicAdd(&gh[ya * T.W + xb], a_hb * s.fx * (1.0f - s.fy));
+    atomicAdd(&gh[yb * T.W + xa], a_hb * (1.0f - s.fx) * s.fy);
+    atomicAdd(&gh[yb * T.W + xb], a_hb * s.fx * s.fy);
+  }
+  // t = texel (1/2 + k step) / cos e (every mode) grows with e; L(e, a)
+  // on the unit sphere
+  const double dte = (double)a_t * (double)t * (double)st.tan_e;
+  ge += dte + (double)a_Lx * (-(double)st.se * st.ca) + (double)a_Ly * (-(double)st.se * st.sa) +
+        (double)a_Lz * (double)st.ce;
+  ga += (double)a_Lx * (-(double)st.ce * st.sa) + (double)a_Ly * ((double)st.ce * st.ca);
+  return a_hp;
+}
+
 template <bool SPHERE, int MODE, bool SAVED>
 __device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, int li, int lj,
                                             const float* __restrict__ gs,
@@ -119,113 +232,14 @@ __device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, i
       unsigned n_lb = 0, n_smp = 0;
       res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab);
     }
-    const float dd = res.alpha * T.inv_rL;
-    if (res.valid && g != 0.0f && fabsf(dd) < 1.0f) {
-      const float t = res.t, u = res.u;
-      const Sample s = sample_at(r, T, t, u);
-      const float dh = s.dh;
-      const float galpha = g * 2.0f * sqrtf(1.0f - dd * dd) * (0.318309886183791f * T.inv_rL);
-      float num, den, x = 0.0f, w = 1.0f;
-      if (SPHERE) {
-        x = t * r.invrho;
-        w = sqrtf(1.0f + x * (2.0f * r.sp + x));
-        num = dh * r.cp;
-        den = t * w - dh * (r.sp + x);
-      } else {
-        num = dh * r.cp;
-        den = t - dh * r.sp;
-      }
-      const float inv2 = 1.0f / (num * num + den * den);
-      const float a_n = galpha * den * inv2;
-      const float a_d = -galpha * num * inv2;
-      float a_dh, a_cp, a_sp, a_t, a_hp = 0.0f;
-      float a_Lx = 0.0f, a_Ly = 0.0f, a_Lz = 0.0f;
-      // bilinear taps
-      const int xa = min(max(s.x0, 0), T.W - 1), xb = min(max(s.x0 + 1, 0), T.W - 1);
-      const int ya = min(max(s.y0, 0), T.H - 1), yb = min(max(s.y0 + 1, 0), T.H - 1);
-      const float h00 = T.h[ya * T.W + xa], h10 = T.h[ya * T.W + xb];
-      const float h01 = T.h[yb * T.W + xa], h11 = T.h[yb * T.W + xb];
-      const float gxh = (1.0f - s.fy) * (h10 - h00) + s.fy * (h11 - h01);
-      const float gyh = (1.0f - s.fx) * (h01 - h00) + s.fx * (h11 - h10);
-      if (SPHERE) {
-        const float X = ((float)i + 0.5f - 0.5f * (float)T.W) * T.texel;
-        const float Y = ((float)j + 0.5f - 0.5f * (float)T.H) * T.texel;
-        const float aa = X * T.invR, bb = Y * T.invR;
-        const float gg = sqrtf(1.0f + aa * aa + bb * bb);
-        const float r1 = 1.0f + hp * T.invR;
-        const float G = gg / (r1 * T.texel);
-        a_dh = a_n * r.cp - a_d * (r.sp + x);
-        a_cp = a_n * dh;
-        a_t = a_d * w;
-        float a_w = a_d * t;
-        a_sp = -a_d * dh;
-        float a_x = -a_d * dh;
-        // dh = dH(t, rho, sp) - (hb - hp)
-        const float a_hb = -a_dh;
-        a_hp += a_dh;
-        const float spx = r.sp + x;
-        const float wm1 = x * (2.0f * r.sp + x) / (w + 1.0f);
-        a_t += a_dh * spx / w;
-        a_sp += a_dh * t / w;
-        float a_rho = a_dh * (wm1 - x * spx / w);
-        a_x += a_w * spx / w;
-        a_sp += a_w * x / w;
-        a_t += a_x * r.invrho;
-        a_rho -= a_x * x * r.invrho;
-        // texture position d = K u(t)
-        const float a_dx = a_hb * gxh, a_dy = a_hb * gyh;
-        const float omc = 1.0f - r.c * u;  // = 1 / (1 + c t)
-        const float k1 = omc * omc;
-        const float aK = a_dx * r.Kx + a_dy * r.Ky;
-        a_t += aK * k1;
-        a_rho -= aK * k1 * x;
-        a_Lx += a_dx * G * u;
-        a_Ly += a_dy * G * u;
-        a_Lz += -G * u * (a_dx * aa + a_dy * bb) - aK * k1 * t * t * (gg * T.invR / r1);
-        // s_p = (aa Lx + bb Ly + Lz)/g and c_p = sqrt(1 - s_p^2)
-        a_sp += -a_cp * r.sp / r.cp;
-        const float ig = 1.0f / gg;
-        a_Lx += a_sp * aa * ig;
-        a_Ly += a_sp * bb * ig;
-        a_Lz += a_sp * ig;
-        a_hp += a_rho;
-        // taps
-        atomicAdd(&gh[ya * T.W + xa], a_hb * (1.0f - s.fx) * (1.0f - s.fy));
-        atomicAdd(&gh[ya * T.W + xb], a_hb * s.fx * (1.0f - s.fy));
-        atomicAdd(&gh[yb * T.W + xa], a_hb * (1.0f - s.fx) * s.fy);
-        atomicAdd(&gh[yb * T.W + xb], a_hb * s.fx * s.fy);
-      } else {
-        a_dh = a_n * r.cp - a_d * r.sp;
-        a_cp = a_n * dh;
-        a_sp = -a_d * dh;
-        a_t = a_d;
-        a_t += a_dh * T.Lz;
-        a_Lz += a_dh * t;
-        const float a_hb = -a_dh;
-        a_hp += a_dh;
-        const float a_dx = a_hb * gxh, a_dy = a_hb * gyh;
-        const float it = 1.0f / T.texel;
-        a_t += (a_dx * T.Lx + a_dy * T.Ly) * it;
-        a_Lx += a_dx * t * it;
-        a_Ly += a_dy * t * it;
-        a_Lz += a_sp;
-        if (r.cp > 0.0f) {
-          a_Lx += a_cp * T.Lx / r.cp;
-          a_Ly += a_cp * T.Ly / r.cp;
-        }
-        atomicAdd(&gh[ya * T.W + xa], a_hb * (1.0f - s.fx) * (1.0f - s.fy));
-        atomicAdd(&gh[ya * T.W + xb], a_hb * s.fx * (1.0f - s.fy));
-        atomicAdd(&gh[yb * T.W + xa], a_hb * (1.0f - s.fx) * s.fy);
-        atomicAdd(&gh[yb * T.W + xb], a_hb * s.fx * s.fy);
-      }
-      atomicAdd(&gh[j * T.W + i], a_hp);
-      // t = texel (1/2 + k step) / cos e (every mode) grows with e; L(e, a)
-      // on the unit sphere
-      const double dte = (double)a_t * (double)t * (double)st.tan_e;
-      ge += dte + (double)a_Lx * (-(double)st.se * st.ca) + (double)a_Ly * (-(double)st.se * st.sa) +
-            (double)a_Lz * (double)st.ce;
-      ga += (double)a_Lx * (-(double)st.ce * st.sa) + (double)a_Ly * ((double)st.ce * st.ca);
+    float X = 0.0f, Y = 0.0f;
+    if (SPHERE) {
+      X = ((float)i + 0.5f - 0.5f * (float)T.W) * T.texel;
+      Y = ((float)j + 0.5f - 0.5f * (float)T.H) * T.texel;
     }
+    const float a_hp = adjoint_sample<SPHERE>(T, st, r, res, g, X, Y, 1.0f + hp * T.invR, gh, ge,
+                                              ga);
+    if (a_hp != 0.0f) atomicAdd(&gh[j * T.W + i], a_hp);
   }
 }
 
@@ -321,6 +335,146 @@ __global__ __launch_bounds__(256) void points_kernel(TileK T, const float2* __re
   }
   if (k >= n) return;
   out[k] = shade_point<SPHERE, MODE>(T, xy[k], tab);
+}
+
+// Adjoint of shadow rays from surface points, the points held fixed: the
+// chain rule of adjoint_sample, with dL/d(origin height) spread over the
+// bilinear taps at the point (the origin sits on the bilinear terrain there).
+// Work is mapped as in points_kernel; the sun gradient is reduced per
+// workgroup as in adjoint_kernel.
+template <bool SPHERE, int MODE, bool IMAGE>
+__global__ __launch_bounds__(256) void points_adjoint_kernel(TileK T, SunTrig st,
+                                                             const float2* __restrict__ xy,
+                                                             long long n, int img_w, int nbx,
+                                                             const float* __restrict__ gs,
+                                                             float* __restrict__ gh,
+                                                             double* __restrict__ gsun) {
+  __shared__ double red[2][4];
+  __shared__ int tab[SS_MAXLEV];
+  if (MODE == SS_MODE_EXACT) {
+    bound_tab_fill(T, tab);
+    __syncthreads();
+  }
+  long long k;
+  bool ok;
+  if (IMAGE) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int bx = (int)(blockIdx.x % (unsigned)nbx), by = (int)(blockIdx.x / (unsigned)nbx);
+    const int px = bx * 16 + (wv & 1) * 8 + (lane & 7);
+    const int py = by * 16 + (wv >> 1) * 8 + (lane >> 3);
+    k = (long long)py * img_w + px;
+    ok = px < img_w && k < n;
+  } else {
+    k = (long long)blockIdx.x * 256 + threadIdx.x;
+    ok = k < n;
+  }
+  double ge = 0.0, ga = 0.0;
+  if (ok) {
+    const float2 q = xy[k];
+    const float g = gs[k];
+    if (q.x == q.x && q.y == q.y && g != 0.0f) {
+      const float qx = fminf(fmaxf(q.x, 0.0f), (float)T.W);
+      const float qy = fminf(fmaxf(q.y, 0.0f), (float)T.H);
+      const int i = min((int)floorf(qx), T.W - 1), j = min((int)floorf(qy), T.H - 1);
+      const float ref = T.h[j * T.W + i];
+      const float ox = qx - ((float)i + 0.5f), oy = qy - ((float)j + 0.5f);
+      const float dz = terrain_above(T, qx, qy, ref);
+      Ray<SPHERE> r;
+      ray_init(T, i, j, ref, r, ox, oy, dz);
+      unsigned n_lb = 0, n_smp = 0;
+      const RayResult res = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab);
+      float X = 0.0f, Y = 0.0f;
+      if (SPHERE) {
+        X = ((float)i + 0.5f + ox - 0.5f * (float)T.W) * T.texel;
+        Y = ((float)j + 0.5f + oy - 0.5f * (float)T.H) * T.texel;
+      }
+      const float a_o = adjoint_sample<SPHERE>(T, st, r, res, g, X, Y,
+                                               1.0f + (ref + dz) * T.invR, gh, ge, ga);
+      if (a_o != 0.0f) {
+        // the origin height is the bilinear terrain at q (taps as terrain_above)
+        const float x = qx - 0.5f, y = qy - 0.5f;
+        const float flx = floorf(x), fly = floorf(y);
+        const float fx = x - flx, fy = y - fly;
+        const int x0 = (int)flx, y0 = (int)fly;
+        const int xa = min(max(x0, 0), T.W - 1), xb = min(max(x0 + 1, 0), T.W - 1);
+        const int ya = min(max(y0, 0), T.H - 1), yb = min(max(y0 + 1, 0), T.H - 1);
+        atomicAdd(&gh[ya * T.W + xa], a_o * (1.0f - fx) * (1.0f - fy));
+        atomicAdd(&gh[ya * T.W + xb], a_o * fx * (1.0f - fy));
+        atomicAdd(&gh[yb * T.W + xa], a_o * (1.0f - fx) * fy);
+        atomicAdd(&gh[yb * T.W + xb], a_o * fx * fy);
+      }
+    }
+  }
+  ge = wave_sum_f64(ge);
+  ga = wave_sum_f64(ga);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = ge;
+    red[1][wave] = ga;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double se = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    const double sa = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    if (se != 0.0 || sa != 0.0) {
+      atomicAdd(&gsun[0], se);
+      atomicAdd(&gsun[1], sa);
+    }
+  }
+}
+
+template <bool SPHERE, int MODE>
+static void points_adjoint_launch(const TileK& T, const SunTrig& st, const float* xy,
+                                  long long n, int img_w, const float* gs, float* gh,
+                                  double* gsun, hipStream_t stream) {
+  const float2* q = reinterpret_cast<const float2*>(xy);
+  if (img_w > 0) {
+    const int nbx = (img_w + 15) / 16;
+    const long long rows = n / img_w, nby = (rows + 15) / 16;
+    hipLaunchKernelGGL((points_adjoint_kernel<SPHERE, MODE, true>), dim3((unsigned)(nbx * nby)),
+                       dim3(256), 0, stream, T, st, q, n, img_w, nbx, gs, gh, gsun);
+  } else {
+    hipLaunchKernelGGL((points_adjoint_kernel<SPHERE, MODE, false>),
+                       dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, T, st, q, n, 0, 1,
+                       gs, gh, gsun);
+  }
+}
+
+template <bool SPHERE>
+static void points_adjoint_mode(const TileK& T, const SunTrig& st, int mode, const float* xy,
+                                long long n, int img_w, const float* gs, float* gh, double* gsun,
+                                hipStream_t stream) {
+  switch (mode) {
+    case SS_MODE_EXACT:
+      points_adjoint_launch<SPHERE, SS_MODE_EXACT>(T, st, xy, n, img_w, gs, gh, gsun, stream);
+      break;
+    case SS_MODE_POINT:
+      points_adjoint_launch<SPHERE, SS_MODE_POINT>(T, st, xy, n, img_w, gs, gh, gsun, stream);
+      break;
+    case SS_MODE_UNIFORM:
+      points_adjoint_launch<SPHERE, SS_MODE_UNIFORM>(T, st, xy, n, img_w, gs, gh, gsun, stream);
+      break;
+    default:
+      points_adjoint_launch<SPHERE, SS_MODE_DP>(T, st, xy, n, img_w, gs, gh, gsun, stream);
+      break;
+  }
+}
+
+hipError_t launch_points_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
+                                 const float* xy, long long n, int img_w, const float* gs,
+                                 float* gh, double* gsun, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  SunTrig st;
+  st.se = (float)sin(elev);
+  st.ce = (float)cos(elev);
+  st.sa = (float)sin(azim);
+  st.ca = (float)cos(azim);
+  st.tan_e = (float)tan(elev);
+  if (sphere)
+    points_adjoint_mode<true>(T, st, mode, xy, n, img_w, gs, gh, gsun, stream);
+  else
+    points_adjoint_mode<false>(T, st, mode, xy, n, img_w, gs, gh, gsun, stream);
+  return hipGetLastError();
 }
 
 template <bool SPHERE, int MODE>

@@ -124,6 +124,14 @@ int main(void) {
   EXPECT(ss_shadow_points(&t, &sun, &p, FAKE(0x400000), -1, FAKE(0x500000), NULL) ==
          SS_ERR_INVALID_ARG);
 
+  EXPECT(ss_shadow_points(&t, &sun, &p, FAKE(0x400000), SS_MAX_POINTS + 1, FAKE(0x500000), NULL) ==
+         SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_points_backward(&t, &sun, &p, FAKE(0x400000), 65, 8, FAKE(0x500000),
+                                   FAKE(0x600000), (double*)FAKE(0x700000), NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_points_backward(&t, &sun, &p, FAKE(0x400000), 64, 0, FAKE(0x500000),
+                                   FAKE(0x600000), (double*)FAKE(0x700004), NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_points_backward(&t, &sun, &p, NULL, 0, 0, NULL, NULL, NULL, NULL) == SS_OK);
+
   EXPECT(ss_shadow_points_image(&t, &sun, &p, FAKE(0x400000), 0, 8, FAKE(0x500000), NULL) ==
          SS_ERR_INVALID_ARG);
   EXPECT(ss_shadow_points_image(&t, &sun, &p, FAKE(0x400004), 8, 8, FAKE(0x500000), NULL) ==

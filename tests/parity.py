@@ -81,3 +81,16 @@ def assert_parity(stats: dict, max_frac_over: float = 2e-3) -> None:
     assert stats["n_over"] <= 4000, stats
     assert stats["unexplained"] == 0, stats
     assert stats["frac_over"] <= max_frac_over, stats
+
+
+def well_conditioned(tr):
+    """Rays whose every oracle decision clears FP32 resolution by a wide margin:
+    lower-bound and clearance gaps (m), rounding of the sample index (half
+    texels), clearance gap between runs (rad), crossing spacing relative to
+    the distance travelled (FP32 offsets carry ~3e-7 relative error), and the
+    deciding sample's distance from a line through texel centres (the bilinear
+    slope, hence the gradient, jumps there).  Used to pick the rays whose
+    gradients the adjoint tests compare."""
+    t = tr.reshape(-1)
+    return ((t["margin_lb"] > 0.05) & (t["margin_dh"] > 0.05) & (t["margin_round"] > 0.01)
+            & (t["margin_seg"] > 2e-5) & (t["margin_geo"] > 2e-5) & (t["margin_tap"] > 2e-5))

@@ -292,3 +292,18 @@ def test_points_image_validation(L):
     for args in [dict(w=0), dict(h=0), dict(w=16385), dict(xy=None), dict(out=None),
                  dict(xy=0x400004)]:
         assert f(**args) == L.SS_ERR_INVALID_ARG, args
+
+
+def test_points_backward_validation(L):
+    lib = L.lib()
+    t, s, p = good(L)
+    f = lambda xy=0x400000, n=64, w=0, g=0x500000, gh=0x600000, gs=0x700000: (  # noqa: E731
+        lib.ss_shadow_points_backward(C.byref(t), C.byref(s), C.byref(p), xy, n, w, g, gh, gs,
+                                      None))
+    for args in [dict(n=-1), dict(w=-1), dict(w=16385), dict(n=65, w=8), dict(n=16385 * 2, w=2),
+                 dict(xy=None), dict(g=None), dict(gh=None), dict(gs=None), dict(xy=0x400004),
+                 dict(gs=0x700004), dict(n=(1 << 36) + 1)]:
+        assert f(**args) == L.SS_ERR_INVALID_ARG, args
+    assert f(n=0, xy=None) == L.SS_OK  # nothing to do, nothing touched
+    assert lib.ss_shadow_points(C.byref(t), C.byref(s), C.byref(p), 0x400000, (1 << 36) + 1,
+                                0x500000, None) == L.SS_ERR_INVALID_ARG

@@ -11,6 +11,7 @@ import torch
 
 import oracle
 from oracle import grad_ref
+from parity import well_conditioned
 
 pytestmark = pytest.mark.gpu
 
@@ -27,18 +28,6 @@ def ss():
 
 def dev():
     return torch.device("cuda:0")
-
-
-def well_conditioned(tr):
-    """Rays whose every oracle decision clears FP32 resolution by a wide margin:
-    lower-bound and clearance gaps (m), rounding of the sample index (half
-    texels), clearance gap between runs (rad), crossing spacing relative to
-    the distance travelled (FP32 offsets carry ~3e-7 relative error), and the
-    deciding sample's distance from a line through texel centres (the bilinear
-    slope, hence the gradient, jumps there)."""
-    t = tr.reshape(-1)
-    return ((t["margin_lb"] > 0.05) & (t["margin_dh"] > 0.05) & (t["margin_round"] > 0.01)
-            & (t["margin_seg"] > 2e-5) & (t["margin_geo"] > 2e-5) & (t["margin_tap"] > 2e-5))
 
 
 def rough(shape, seed, amp):

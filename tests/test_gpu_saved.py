@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from test_gpu_adjoint import well_conditioned
+from parity import well_conditioned
 
 pytestmark = pytest.mark.gpu
 
