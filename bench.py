@@ -358,17 +358,26 @@ def cpu_uniform_baseline(h_np, params_or, seconds=5.0):
 
 
 def leg_cold_maxmip(ss, h, mm, mm_bytes, reps=5):
-    """Mipmap build after streaming 1 GiB through the caches (L2 and MALL cold)."""
+    """Mipmap build after reading 1 GiB through the caches: L2 and MALL then hold none of the
+    tile, and (a read leaves clean lines) nothing of the flush is written back inside the timed
+    build.  Flushing by writing instead charges the build with that write-back (about twice the
+    time at 4096^2)."""
     import torch
-    scratch = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=h.device)
+    scratch = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=h.device)
     ts = []
-    for i in range(reps):
-        scratch.fill_(float(i))
+    for _ in range(reps):
+        scratch.sum()
         ts += _timed(lambda: ss.maxmip(h, out=mm), 1)
     del scratch
     ms = float(sum(ts) / len(ts))
     return {"avg_launch_ms": ms, "achieved_GBs": mm_bytes / (ms / 1e3) / 1e9,
-            "frac": mm_bytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS}
+            "frac": mm_bytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, "flush": "read 1 GiB"}
+
+
+def maxmip_bytes(ss, W, H):
+    """Algorithmic HBM bytes of one build: the tile read once, levels >= 1 written once."""
+    return 4 * W * H + 4 * sum(((W + (1 << m) - 1) >> m) * ((H + (1 << m) - 1) >> m)
+                               for m in range(1, ss.maxmip_levels(W, H)))
 
 
 def leg_diff(ss, reps=5):
@@ -560,6 +569,10 @@ def leg_polar(ss, reps=3):
 
     fwd()
     tf = _timed(fwd, reps)
+    mm_b = maxmip_bytes(ss, W, H)
+    t_mm = min(_timed(lambda: ss.maxmip(h, out=mm), 3))
+    mm_res = {"warm_ms": t_mm, "warm_frac": mm_b / (t_mm / 1e3) / 1e9 / PEAK_HBM_GBS,
+              "cold": leg_cold_maxmip(ss, h, mm, mm_b, reps=3)}
     g = torch.ones_like(h)
     gh = torch.zeros_like(h)
     gs = torch.zeros(2, dtype=torch.float64, device=h.device)
@@ -580,7 +593,7 @@ def leg_polar(ss, reps=3):
     tx = _timed(lambda: ss.shadow_cast(h, D, e, a, r, px, mm=mm, out=out, bound=bound), 1)
     res = {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
            "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "mean_s": mean_s,
-           "exact_mrays_s": n / (min(tx) / 1e3) / 1e6, "exact_ms": min(tx)}
+           "exact_mrays_s": n / (min(tx) / 1e3) / 1e6, "exact_ms": min(tx), "maxmip": mm_res}
     del bound
     del h, mm, out, g, gh
     return res
@@ -724,8 +737,7 @@ def main():
                 "avg_launch_ms": avg_dp_ms, "lb_evals_per_ray": n_lb / (W * H),
                 "samples_per_ray": n_smp / (W * H),
                 "ops_model": {"lb": OPS_LB, "sample": OPS_SAMPLE, "ray": OPS_RAY}}
-    mm_bytes = 4.0 * W * H + 4.0 * sum(
-        ((W + (1 << m) - 1) >> m) * ((H + (1 << m) - 1) >> m) for m in range(1, ss.maxmip_levels(W, H)))
+    mm_bytes = float(maxmip_bytes(ss, W, H))
     maxmip = {"bound": "hbm", "avg_launch_ms": avg_mm_ms,
               "achieved_GBs": mm_bytes / (avg_mm_ms / 1e3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
               "frac": mm_bytes / (avg_mm_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
