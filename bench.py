@@ -7,8 +7,11 @@ Workload (the 4096^2 tile configuration): a 4096 x 4096 fp32 DEM at 5 m/texel
 radius 0.267 degrees, shadow rays capped at 30 km of horizontal travel.
 
 One step = build the maximum mipmap + run the descent forward for all 8 suns
-(8 x 16.8 M rays).  `value` is rays per second of the whole step, inputs
-resident in HBM.  Beside it the JSON line reports uniform stepping on the same
+(8 x 16.8 M rays), as one replay of the batched plan's HIP graph (the build,
+then one persistent launch over every ray block of the 8 suns).  `value` is
+rays per second of the whole step, inputs resident in HBM.  The same work as
+eight per-sun launches of the per-tile kernel is timed beside it (bit-identical
+outputs).  Beside it the JSON line reports uniform stepping on the same
 suns (the paper's baseline), forward+backward throughput, the roofline of the
 dominant kernel, and the FP64 CPU oracle timed on a bounded sample.
 
@@ -55,14 +58,16 @@ def src_hash(paths):
     return h.hexdigest()[:16]
 
 
-DP_SOURCES = ["paper_2005_06671_amd/csrc/ray.h", "paper_2005_06671_amd/csrc/shadow.hip",
+DP_SOURCES = ["paper_2005_06671_amd/csrc/ray.h", "paper_2005_06671_amd/csrc/batched.hip",
               "paper_2005_06671_amd/csrc/common.h"]
+TRAFFIC_FILE = "descent_tile_traffic.json"
+COUNTERS_FILE = "descent_tile_counters.txt"
 
 
 def traffic_from_profile():
-    """HBM bytes per launch of the descent kernel from the committed counter
+    """HBM bytes per launch of the batched descent kernel from the committed counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "shadow_dp_tile_traffic.json")
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     try:
         with open(path) as f:
             d = json.load(f)
@@ -151,36 +156,45 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, counters_dir, out_dir):
         wb = sum(write.get(name, [0.0])) / max(1, len(write.get(name, []))) * 1024 * cal_w
         out["kernels"][name] = {"launches": len(fetch[name]), "fetch_bytes": fb,
                                 "write_bytes": wb}
-    dp = [k for k in out["kernels"] if "shadow_kernel<true, 8, 0, 0>" in k]
+    dp = [k for k in out["kernels"] if "batched_kernel" in k]
     if dp:
         k = out["kernels"][dp[0]]
         out["hbm_bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
+        out["kernel"] = dp[0]
     out["command"] = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-include-regex 'ss::|copy' "
                       "--output-format csv -d <dir> -o bench -- python bench.py --steps 1 --warmup 0 "
                       "--no-cpu --no-extras --calibrate-copy --dem-cache /tmp/dem_tile.npy")
-    with open(os.path.join(out_dir, "shadow_dp_tile_traffic.json"), "w") as f:
+    with open(os.path.join(out_dir, TRAFFIC_FILE), "w") as f:
         json.dump(out, f, indent=1)
     if counters_dir:
-        acc = collections.defaultdict(lambda: collections.defaultdict(list))
-        for r in _csv_rows(os.path.join(counters_dir, "bench_counter_collection.csv")):
-            acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
-        lines = ["kernel | VALU instr per wave | active lanes per VALU instr | trans per wave | "
-                 "L2 hit rate"]
-        for name, d in acc.items():
-            v = {c: sum(x) / len(x) for c, x in d.items()}
-            waves = v.get("SQ_WAVES", 1.0)
-            hit = v.get("TCC_HIT_sum")
-            miss = v.get("TCC_MISS_sum")
-            hr = f"{hit / (hit + miss):.3f}" if hit is not None and miss is not None else "-"
-            lines.append(f"{name[:70]} | {v.get('SQ_INSTS_VALU', 0) / waves:.0f} | "
-                         f"{v.get('SQ_THREAD_CYCLES_VALU', 0) / max(1.0, v.get('SQ_ACTIVE_INST_VALU', 1)):.1f} | "
-                         f"{v.get('SQ_INSTS_VALU_TRANS_F32', 0) / waves:.0f} | {hr}")
-        with open(os.path.join(out_dir, "shadow_dp_tile_counters.txt"), "w") as f:
-            f.write("# rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU "
-                    "SQ_INSTS_VALU_TRANS_F32 TCC_HIT_sum TCC_MISS_sum --kernel-include-regex "
-                    "shadow_kernel --output-format csv -d <dir> -o bench -- python bench.py --steps 1 "
-                    "--warmup 0 --no-cpu --no-extras --dem-cache /tmp/dem_tile.npy\n")
-            f.write("\n".join(lines) + "\n")
+        summarize_counters(os.path.join(counters_dir, "bench_counter_collection.csv"), out_dir)
+
+
+def summarize_counters(csv_path, out_dir):
+    """VALU and L2 counters per kernel (averaged over its dispatches).  A persistent
+    kernel's waves each run many ray blocks, so compare its total, not per-wave, counts."""
+    import collections
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in _csv_rows(csv_path):
+        acc[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["kernel | VALU instr per dispatch | waves | VALU instr per wave | "
+             "active lanes per VALU instr | trans per wave | L2 hit rate"]
+    for name, d in acc.items():
+        v = {c: sum(x) / len(x) for c, x in d.items()}
+        waves = v.get("SQ_WAVES", 1.0)
+        hit = v.get("TCC_HIT_sum")
+        miss = v.get("TCC_MISS_sum")
+        hr = f"{hit / (hit + miss):.3f}" if hit is not None and miss is not None else "-"
+        lines.append(f"{name[:70]} | {v.get('SQ_INSTS_VALU', 0):.4g} | {waves:.0f} | "
+                     f"{v.get('SQ_INSTS_VALU', 0) / waves:.0f} | "
+                     f"{v.get('SQ_THREAD_CYCLES_VALU', 0) / max(1.0, v.get('SQ_ACTIVE_INST_VALU', 1)):.1f} | "
+                     f"{v.get('SQ_INSTS_VALU_TRANS_F32', 0) / waves:.0f} | {hr}")
+    with open(os.path.join(out_dir, COUNTERS_FILE), "w") as f:
+        f.write("# rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU "
+                "SQ_INSTS_VALU_TRANS_F32 TCC_HIT_sum TCC_MISS_sum --kernel-include-regex "
+                "'batched_kernel|shadow_kernel' --output-format csv -d <dir> -o bench -- python "
+                "bench.py --steps 1 --warmup 0 --no-cpu --no-extras --dem-cache /tmp/dem_tile.npy\n")
+        f.write("\n".join(lines) + "\n")
 
 
 def _pct(xs):
@@ -688,11 +702,35 @@ def main():
     def pair():
         return (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
 
-    # events for every launch of the timed region, read after it ends
-    ev_dp = [[pair() for _ in suns] for _ in range(args.steps)]
-    ev_mm = [pair() for _ in range(args.steps)]
+    # The step: one replay of the batched plan's graph (max-mip build, queue reset, one
+    # persistent launch over every ray block of the 8 suns).  Outputs equal the per-sun
+    # launches below bit for bit; the persistent launch has one tail instead of eight.
+    plan = ss.BatchedPlan([h], [D], suns, params, outs=[outs], mms=[mm])
+    ev_step = [pair() for _ in range(args.steps)]
 
-    def step(i=None):
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev_step[i][0].record(stream)
+        plan.launch()
+        ev_step[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / max(1, args.steps)
+    value = rays_per_step / (ms_per_step / 1e3) / 1e6
+    step_ms = [a.elapsed_time(b) for a, b in ev_step]
+    avg_step_ms = float(np.mean(step_ms))
+    plan_cfg = plan.config()
+
+    # the same work as eight per-sun launches of the per-tile kernel (after the timed region)
+    reps = max(2, min(args.steps, 5))
+    ev_dp = [[pair() for _ in suns] for _ in range(reps)]
+    ev_mm = [pair() for _ in range(reps)]
+    outs_ps = [torch.empty_like(h) for _ in suns]
+
+    def per_sun_step(i=None):
         if i is not None:
             ev_mm[i][0].record(stream)
         ss.maxmip(h, out=mm)
@@ -701,72 +739,91 @@ def main():
         for k, (e, a, r) in enumerate(suns):
             if i is not None:
                 ev_dp[i][k][0].record(stream)
-            ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
+            ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs_ps[k])
             if i is not None:
                 ev_dp[i][k][1].record(stream)
 
-    for _ in range(args.warmup):
-        step()
+    per_sun_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
+    for i in range(reps):
+        per_sun_step(i)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / max(1, args.steps)
-    value = rays_per_step / (ms_per_step / 1e3) / 1e6
+    ps_ms = (time.perf_counter() - t0) * 1e3 / reps
     launch_ms = [a.elapsed_time(b) for row in ev_dp for a, b in row]
     maxmip_ms = [a.elapsed_time(b) for a, b in ev_mm]
     avg_dp_ms = float(np.mean(launch_ms))
     avg_mm_ms = float(np.mean(maxmip_ms))
-    step_ms = [ev_mm[i][0].elapsed_time(ev_dp[i][-1][1]) for i in range(args.steps)]
+    same = all(torch.equal(outs[k].view(torch.int32), outs_ps[k].view(torch.int32))
+               for k in range(len(suns)))
+    if not same:
+        raise RuntimeError("batched and per-sun launches disagree")
+    del outs_ps
+    plan.close()
 
-    # algorithmic units per launch (instrumented twin of the same kernel, untimed)
+    # algorithmic units of the step (instrumented twin of the same per-ray code, untimed)
     units = []
     for k, (e, a, r) in enumerate(suns):
         _, cnt = ss.shadow_cast_counted(h, D, e, a, r, params, mm=mm)
         units.append([int(x) for x in cnt.cpu().tolist()])
-    n_lb = float(np.mean([u[0] for u in units]))
-    n_smp = float(np.mean([u[1] for u in units]))
-    ops_per_launch = OPS_LB * n_lb + OPS_SAMPLE * n_smp + OPS_RAY * W * H
-    achieved = ops_per_launch / (avg_dp_ms / 1e3) / 1e12
+    n_lb = float(np.sum([u[0] for u in units]))
+    n_smp = float(np.sum([u[1] for u in units]))
+    ops_per_step = OPS_LB * n_lb + OPS_SAMPLE * n_smp + OPS_RAY * rays_per_step
+    # the events bracket the whole graph, so the max-mip build and the queue reset
+    # (about 0.2% of it) count as kernel time: the figure errs low
+    achieved = ops_per_step / (avg_step_ms / 1e3) / 1e12
     traffic = traffic_from_profile()
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                 "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic,
-                "kernel": "shadow_kernel<sphere, 8x8, descent, plain>",
-                "avg_launch_ms": avg_dp_ms, "lb_evals_per_ray": n_lb / (W * H),
-                "samples_per_ray": n_smp / (W * H),
-                "ops_model": {"lb": OPS_LB, "sample": OPS_SAMPLE, "ray": OPS_RAY}}
+                "kernel": "batched_kernel<descent> (one persistent launch over the 8 suns)",
+                "avg_launch_ms": avg_step_ms, "timed_span": "graph replay incl. max-mip build",
+                "lb_evals_per_ray": n_lb / rays_per_step, "samples_per_ray": n_smp / rays_per_step,
+                "ops_model": {"lb": OPS_LB, "sample": OPS_SAMPLE, "ray": OPS_RAY},
+                "plan_ray_tile_fuse_depth": list(plan_cfg)}
     mm_bytes = float(maxmip_bytes(ss, W, H))
     maxmip = {"bound": "hbm", "avg_launch_ms": avg_mm_ms,
               "achieved_GBs": mm_bytes / (avg_mm_ms / 1e3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
               "frac": mm_bytes / (avg_mm_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
               "note": "64 MiB source is L2/MALL resident between steps (warm)"}
-
-    extras = {"step_ms_p10_p50_p90": _pct(step_ms), "launch_ms_p10_p50_p90": _pct(launch_ms),
-              "launch_ms_per_sun": [float(np.mean([ev_dp[i][k][0].elapsed_time(ev_dp[i][k][1])
-                                                   for i in range(args.steps)]))
-                                    for k in range(len(suns))]}
+    ps_ops = ops_per_step / len(suns)
+    extras = {"step_ms_p10_p50_p90": _pct(step_ms),
+              "per_sun_launches": {
+                  "ms_per_step": ps_ms, "mrays_s": rays_per_step / (ps_ms / 1e3) / 1e6,
+                  "kernel": "shadow_kernel<sphere, 8x8, descent, plain>",
+                  "avg_launch_ms": avg_dp_ms, "launch_ms_p10_p50_p90": _pct(launch_ms),
+                  "launch_ms_per_sun": [float(np.mean([ev_dp[i][k][0].elapsed_time(ev_dp[i][k][1])
+                                                       for i in range(reps)]))
+                                        for k in range(len(suns))],
+                  "roofline_frac": ps_ops / (avg_dp_ms / 1e3) / 1e12 / PEAK_VALU_TOPS,
+                  "outputs_equal_batched": same}}
     if not args.no_extras:
         extras["accuracy_vs_dense"], extras["exact_mode"] = leg_accuracy(ss, h, mm, D, suns, c)
         maxmip["cold"] = leg_cold_maxmip(ss, h, mm, mm_bytes)
         extras["schedule_study"] = leg_schedules(ss, h, mm, D, suns)
-        extras["gather_ceiling"] = leg_gather(ss, dev, W * H, W * H + ss.maxmip_floats(W, H),
-                                              roofline)
+        extras["gather_ceiling"] = leg_gather(ss, dev, rays_per_step,
+                                              W * H + ss.maxmip_floats(W, H), roofline)
         # uniform stepping, one texel per step, same suns, cap and exits
+        # (both launch shapes: the batched call, as the step, and per-sun launches)
         pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
         for k, (e, a, r) in enumerate(suns[:1]):
             ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=outs[k])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ss.shadow_cast_batched([h], [D], suns, pu, outs=[outs], mms=[mm])
+        torch.cuda.synchronize()
+        tu = time.perf_counter() - t0
+        t0 = time.perf_counter()
         ss.maxmip(h, out=mm)
         for k, (e, a, r) in enumerate(suns):
             ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=outs[k])
         torch.cuda.synchronize()
-        tu = time.perf_counter() - t0
+        tu_ps = time.perf_counter() - t0
         uniform = rays_per_step / tu / 1e6
         extras["uniform_mrays_s"] = uniform
         extras["speedup_vs_uniform"] = value / uniform
+        extras["per_sun_launches"]["uniform_mrays_s"] = rays_per_step / tu_ps / 1e6
+        extras["per_sun_launches"]["speedup_vs_uniform"] = (
+            extras["per_sun_launches"]["mrays_s"] / (rays_per_step / tu_ps / 1e6))
         ucnt = []
         for k, (e, a, r) in enumerate(suns[:2]):
             _, cnt = ss.shadow_cast_counted(h, D, e, a, r, pu, mm=mm)

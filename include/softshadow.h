@@ -38,7 +38,7 @@ extern "C" {
 #define SS_ERR_INVALID_ARG (-1)  /* a pointer, size or parameter is out of range */
 #define SS_ERR_HIP (-2)          /* the HIP runtime reported an error; see ss_status_string */
 #define SS_ERR_WORKSPACE (-3)    /* workspace missing or smaller than required */
-#define SS_ERR_UNSUPPORTED (-4)  /* a combination this build does not implement */
+#define SS_ERR_UNSUPPORTED (-4)  /* a combination the library does not implement */
 
 #define SS_MODE_DP 0             /* dynamic-programming descent (Sec. 3.2, Alg. 1) */
 #define SS_MODE_UNIFORM 1        /* uniform stepping baseline (Sec. 2, Fig. 1b; Sec. 6.3) */

@@ -564,8 +564,10 @@ extern "C" int32_t ss_shadow_cast_backward_saved(const ss_tile* tile, const ss_s
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Workspace: SS_NXCD queue counters, then the tables (pair parameter blocks, output
+// pointers, item prefix sums, per-XCD band prefix sums, block-grid widths).
 struct WsLayout {
-  size_t counter, pairs, outs, start, nbx, total;
+  size_t counter, pairs, outs, start, xstart, nbx, total;
 };
 
 static bool ws_layout(int32_t n_tiles, int32_t n_suns, WsLayout* L) {
@@ -575,7 +577,8 @@ static bool ws_layout(int32_t n_tiles, int32_t n_suns, WsLayout* L) {
   L->pairs = 256;
   L->outs = L->pairs + align256(np * sizeof(TileK));
   L->start = L->outs + align256(np * sizeof(float*));
-  L->nbx = L->start + align256((np + 1) * sizeof(long long));
+  L->xstart = L->start + align256((np + 1) * sizeof(long long));
+  L->nbx = L->xstart + align256((size_t)SS_NXCD * (np + 1) * sizeof(long long));
   L->total = L->nbx + align256(np * sizeof(int));
   return true;
 }
@@ -607,6 +610,7 @@ static int32_t build_tables(const ss_tile* tiles, int32_t n_tiles, const ss_sun*
   TileK* pairs = reinterpret_cast<TileK*>(base + L.pairs);
   float** outs = reinterpret_cast<float**>(base + L.outs);
   long long* start = reinterpret_cast<long long*>(base + L.start);
+  long long* xstart = reinterpret_cast<long long*>(base + L.xstart);
   int* nbxs = reinterpret_cast<int*>(base + L.nbx);
   long long items = 0;
   for (int t = 0; t < n_tiles; ++t) {
@@ -624,11 +628,21 @@ static int32_t build_tables(const ss_tile* tiles, int32_t n_tiles, const ss_sun*
     }
   }
   start[np] = items;
+  // XCD x's queue: band x of every pair, [x n / SS_NXCD, (x + 1) n / SS_NXCD) of its n items
+  for (int x = 0; x < SS_NXCD; ++x) {
+    long long* row = xstart + (size_t)x * (np + 1);
+    long long q = 0;
+    for (size_t p = 0; p < np; ++p) {
+      const long long n = start[p + 1] - start[p];
+      row[p] = q;
+      q += (long long)(x + 1) * n / SS_NXCD - (long long)x * n / SS_NXCD;
+    }
+    row[np] = q;
+  }
   bt->bd.n_pairs = (int)np;
   bt->bd.n_tiles = n_tiles;
   bt->bd.n_suns = n_suns;
   bt->bd.total_items = items;
-  bt->bd.item_limit = items;
   return SS_OK;
 }
 
@@ -676,10 +690,11 @@ static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchT
                              const_cast<float*>(tiles[t].bound), stream)))
       return rc;
   }
-  SS_HIP(launch_fill_u32(reinterpret_cast<unsigned int*>(ws + L.counter), 0u, 1, stream));
+  SS_HIP(launch_fill_u32(reinterpret_cast<unsigned int*>(ws + L.counter), 0u, SS_NXCD, stream));
   SS_HIP(launch_batched(reinterpret_cast<const TileK*>(ws + L.pairs),
                         reinterpret_cast<float* const*>(ws + L.outs),
                         reinterpret_cast<const long long*>(ws + L.start),
+                        reinterpret_cast<const long long*>(ws + L.xstart),
                         reinterpret_cast<const int*>(ws + L.nbx),
                         reinterpret_cast<unsigned int*>(ws + L.counter), bt.bd, bt.rp.sphere,
                         bt.rp.mode, bt.rp.ray_tile, n_wg, stream));
@@ -806,20 +821,19 @@ struct EventPair {
   }
 };
 
-// Times each ray-tile shape on the largest tile with its middle sun, and each
-// fusion depth on that tile's mipmap; the choices never change results.
+// Times each fusion depth on the largest tile's mipmap, and each ray-tile shape
+// with the batched kernel itself on the largest tile and up to 8 of the suns
+// (spread over the list); the choices never change results.
 static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n_suns,
-                    const ss_params* params, const Resolved& rp, float* const* d_shadow,
+                    const ss_params* params, float* const* d_shadow, unsigned char* ws,
                     hipStream_t s, int* best_tile, int* best_fuse) {
   int big = 0;
   for (int t = 1; t < n_tiles; ++t)
     if ((int64_t)tiles[t].width * tiles[t].rows > (int64_t)tiles[big].width * tiles[big].rows) big = t;
-  const int ks = n_suns / 2;
   EventPair ev;
   SS_HIP(hipEventCreate(&ev.a));
   SS_HIP(hipEventCreate(&ev.b));
   const hipEvent_t a = ev.a, b = ev.b;
-  float* out = d_shadow[(size_t)big * n_suns + ks];
   // fusion depth
   double best = 1e30;
   *best_fuse = 6;
@@ -839,19 +853,31 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
       }
     }
   }
-  // ray-tile shape
+  // ray-tile shape: the persistent kernel over (largest tile) x (sun subset); the
+  // sub-batch's workspace fits in the caller's (fewer pairs)
+  const int ns = n_suns < 8 ? n_suns : 8;
+  std::vector<ss_sun> sub(ns);
+  std::vector<float*> sub_out(ns);
+  for (int k = 0; k < ns; ++k) {
+    const int idx = (int)(((int64_t)k * n_suns) / ns);
+    sub[k] = suns[idx];
+    sub_out[k] = d_shadow[(size_t)big * n_suns + idx];
+  }
+  WsLayout L;
+  ws_layout(1, ns, &L);
   best = 1e30;
   *best_tile = SS_TILE_8x8;
   const int shapes[4] = {SS_TILE_8x8, SS_TILE_16x4, SS_TILE_4x16, SS_TILE_32x2};
-  Resolved r2 = rp;
   for (int sh : shapes) {
-    r2.ray_tile = sh;
-    TileK K;
-    int32_t rc = make_tilek(&tiles[big], &suns[ks], r2, params->max_len_m, params->body_radius_m, &K);
+    BatchTables bt;
+    int32_t rc = build_tables(&tiles[big], 1, sub.data(), ns, params, sub_out.data(), sh, &bt);
     if (rc) return rc;
-    for (int rep = 0; rep < 2; ++rep) {
+    SS_HIP(hipStreamSynchronize(s));
+    SS_HIP(hipMemcpy(ws + L.pairs, bt.bytes.data(), bt.bytes.size(), hipMemcpyHostToDevice));
+    const int n_wg = batched_workgroups(bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile);
+    for (int rep = 0; rep < 3; ++rep) {
       SS_HIP(hipEventRecord(a, s));
-      SS_HIP(launch_forward(K, r2.sphere, r2.mode, sh, false, out, nullptr, nullptr, s));
+      if ((rc = enqueue_batch(&tiles[big], 1, bt, ws, *best_fuse, n_wg, s))) return rc;
       SS_HIP(hipEventRecord(b, s));
       double ms = 0.0;
       SS_HIP(time_ms(a, b, &ms));
@@ -909,7 +935,8 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
   }
   if (!cached) {
     int bt_code = 0, bf = 6;
-    rc = tune(tiles, n_tiles, suns, n_suns, params, rp, d_shadow, s, &bt_code, &bf);
+    rc = tune(tiles, n_tiles, suns, n_suns, params, d_shadow,
+              static_cast<unsigned char*>(d_workspace), s, &bt_code, &bf);
     if (rc) return rc;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -39,12 +39,15 @@ hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, do
 struct BatchDesc {
   int n_pairs;            // tiles * suns
   int n_tiles, n_suns;
-  long long total_items;  // sum over pairs of ray blocks
-  long long item_limit;   // process items [0, item_limit) (tuning); = total_items normally
+  long long total_items;  // sum over pairs of their items (groups of SS_ITEM_BLOCKS ray blocks)
 };
+// d_xstart: SS_NXCD rows of n_pairs + 1 prefix sums, row x = the items of band x of
+// each pair (band x of a pair: its items [x n / SS_NXCD, (x + 1) n / SS_NXCD));
+// d_counter: SS_NXCD queue counters, zero at launch.
 hipError_t launch_batched(const TileK* d_pairs, float* const* d_out_ptrs, const long long* d_item_start,
-                          const int* d_pair_nbx, unsigned int* d_counter, const BatchDesc& bd,
-                          bool sphere, int mode, int ray_tile, int n_workgroups, hipStream_t stream);
+                          const long long* d_xstart, const int* d_pair_nbx, unsigned int* d_counter,
+                          const BatchDesc& bd, bool sphere, int mode, int ray_tile, int n_workgroups,
+                          hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream);
 int batched_workgroups(bool sphere, int mode, int ray_tile);
 
@@ -87,6 +90,7 @@ hipError_t launch_resample(const ResampleK& K, hipStream_t stream);
 hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
                                float* out, long long n_threads, hipStream_t stream);
 
-#define SS_ITEM_BLOCKS 4  // ray blocks (256 rays each) per queue item of the batched kernel
+#define SS_ITEM_BLOCKS 1  // ray blocks (256 rays each) per queue item of the batched kernel
+#define SS_NXCD 8         // XCDs; workgroup ids are dealt round-robin over them
 
 }  // namespace ss
