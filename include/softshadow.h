@@ -343,6 +343,12 @@ int32_t ss_batched_plan_destroy(ss_plan* plan);
 int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t window, int32_t iters,
                         float* d_out, int64_t n_threads, void* stream);
 
+/* FP32 VALU probe used to check the arithmetic peak a roofline divides by (not
+ * part of the method): n_workgroups x 256 lanes each run 32 x iters non-packed
+ * FP32 FMAs in eight independent chains; d_out[n_workgroups * 256] receives
+ * the lanes' sums.  Rate = 8192 n_workgroups iters / time lane-FMAs per second. */
+int32_t ss_probe_valu(int32_t iters, int64_t n_workgroups, float* d_out, void* stream);
+
 /* Text for a status code (for SS_ERR_HIP: the last HIP error of this thread). */
 const char* ss_status_string(int32_t status);
 

@@ -433,6 +433,20 @@ def shadow_points_image(h: torch.Tensor, texel_m: float, elev: float, azim: floa
     return out
 
 
+def probe_valu(iters: int = 4096, n_workgroups: int = 8192, device=None,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """FP32 VALU probe (ss_probe_valu): 32 * iters FMAs per lane over n_workgroups x 256 lanes;
+    returns the per-lane sums."""
+    n = int(n_workgroups) * 256
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=device or "cuda")
+    elif out.numel() < n or not out.is_cuda or out.dtype != torch.float32:
+        raise ValueError("out must be float32 CUDA with n_workgroups * 256 elements")
+    L.check("ss_probe_valu", L.lib().ss_probe_valu(int(iters), int(n_workgroups), out.data_ptr(),
+                                                   _stream(out.device)))
+    return out
+
+
 def probe_gather(src: torch.Tensor, window: int = 0, iters: int = 64, n_threads: int = 1 << 21,
                  out: torch.Tensor | None = None) -> torch.Tensor:
     """Memory-system gather probe (ss_probe_gather); returns the per-lane sums."""

@@ -542,6 +542,12 @@ extern "C" int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t
   return SS_OK;
 }
 
+extern "C" int32_t ss_probe_valu(int32_t iters, int64_t n_workgroups, float* d_out, void* stream) {
+  if (!d_out || iters < 1 || n_workgroups < 1 || n_workgroups > 0x7fffffffLL) return SS_ERR_INVALID_ARG;
+  SS_HIP(launch_valu_probe(iters, n_workgroups, d_out, (hipStream_t)stream));
+  return SS_OK;
+}
+
 extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun,
                                            const ss_params* params, const float* d_grad_shadow,
                                            float* d_grad_height, double* d_grad_sun, void* stream) {

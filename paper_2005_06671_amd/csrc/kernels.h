@@ -89,6 +89,7 @@ hipError_t launch_resample(const ResampleK& K, hipStream_t stream);
 // Gather throughput probe (measurement only).
 hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
                                float* out, long long n_threads, hipStream_t stream);
+hipError_t launch_valu_probe(int iters, long long n_workgroups, float* out, hipStream_t stream);
 
 #define SS_ITEM_BLOCKS 1  // ray blocks (256 rays each) per queue item of the batched kernel
 #define SS_NXCD 8         // XCDs; workgroup ids are dealt round-robin over them

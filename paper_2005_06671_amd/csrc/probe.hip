@@ -1,9 +1,13 @@
-// Gather throughput probe for the memory system (a measurement tool, not part
-// of the method): every lane walks an xorshift sequence and sums the floats
-// it addresses, so no index array competes with the gathers for bandwidth.
-// Indices cover the largest power of two <= n floats, or a window of
-// `window` floats (a power of two) chosen per lane; iters is rounded up to a
-// multiple of 8.
+// Measurement probes (tools, not part of the method).
+//
+// Gather throughput of the memory system: every lane walks an xorshift
+// sequence and sums the floats it addresses, so no index array competes with
+// the gathers for bandwidth.  Indices cover the largest power of two <= n
+// floats, or a window of `window` floats (a power of two) chosen per lane;
+// iters is rounded up to a multiple of 8.
+//
+// FP32 VALU rate: every lane runs eight independent chains of non-packed FMAs
+// (32 per iteration), enough independent work to keep a SIMD issuing.
 #include "kernels.h"
 
 namespace ss {
@@ -40,6 +44,33 @@ hipError_t launch_gather_probe(const float* src, long long n_floats, long long w
   const unsigned nwin = window > 0 ? (unsigned)(p / (unsigned long long)window) : 1u;
   hipLaunchKernelGGL(gather_probe_kernel, dim3((unsigned)(n_threads / 256)), dim3(256), 0, stream,
                      src, mask, wmask, nwin, iters, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void valu_probe_kernel(int iters, float a, float b,
+                                                         float* __restrict__ out) {
+  const float x = (float)threadIdx.x * 1e-3f;
+  float c0 = x, c1 = x + 1.0f, c2 = x + 2.0f, c3 = x + 3.0f;
+  float c4 = x + 4.0f, c5 = x + 5.0f, c6 = x + 6.0f, c7 = x + 7.0f;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      c0 = fmaf(c0, a, b);
+      c1 = fmaf(c1, a, b);
+      c2 = fmaf(c2, a, b);
+      c3 = fmaf(c3, a, b);
+      c4 = fmaf(c4, a, b);
+      c5 = fmaf(c5, a, b);
+      c6 = fmaf(c6, a, b);
+      c7 = fmaf(c7, a, b);
+    }
+  }
+  out[(size_t)blockIdx.x * 256 + threadIdx.x] = ((c0 + c1) + (c2 + c3)) + ((c4 + c5) + (c6 + c7));
+}
+
+hipError_t launch_valu_probe(int iters, long long n_workgroups, float* out, hipStream_t stream) {
+  hipLaunchKernelGGL(valu_probe_kernel, dim3((unsigned)n_workgroups), dim3(256), 0, stream, iters,
+                     0.999f, 0.001f, out);
   return hipGetLastError();
 }
 

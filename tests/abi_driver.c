@@ -202,6 +202,8 @@ int main(void) {
 
   /* probe */
   EXPECT(ss_probe_gather(NULL, 1024, 0, 8, FAKE(0x200000), 256, NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_probe_valu(0, 8, FAKE(0x200000), NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_probe_valu(16, 8, NULL, NULL) == SS_ERR_INVALID_ARG);
 
   if (fails) return 1;
   printf("ok\n");

@@ -307,3 +307,9 @@ def test_points_backward_validation(L):
     assert f(n=0, xy=None) == L.SS_OK  # nothing to do, nothing touched
     assert lib.ss_shadow_points(C.byref(t), C.byref(s), C.byref(p), 0x400000, (1 << 36) + 1,
                                 0x500000, None) == L.SS_ERR_INVALID_ARG
+
+
+def test_valu_probe_validation(L):
+    lib = L.lib()
+    for args in [(0, 8, 0x400000), (16, 0, 0x400000), (16, 1 << 31, 0x400000), (16, 8, None)]:
+        assert lib.ss_probe_valu(*args, None) == L.SS_ERR_INVALID_ARG, args

@@ -126,3 +126,21 @@ def test_gather_probe_sums(ss):
         out = ss.probe_gather(src, win, iters=12, n_threads=1 << 14)
         torch.cuda.synchronize()
         assert torch.all(out == 16.0), win
+
+
+def test_valu_probe_runs_its_chains(ss):
+    """The FP32 VALU probe: every lane's eight chains x -> a x + b (a = 0.999, b = 0.001 in
+    FP32), 4 * iters steps each (float64 reference of the same recurrence)."""
+    iters = 64
+    out = ss.probe_valu(iters, 16)
+    torch.cuda.synchronize()
+    a, b = float(np.float32(0.999)), float(np.float32(0.001))  # the kernel's FP32 constants
+    x0 = torch.arange(256, dtype=torch.float64) * 1e-3
+    ref = torch.zeros(256, dtype=torch.float64)
+    for c in range(8):
+        v = x0 + c
+        for _ in range(4 * iters):
+            v = v * a + b
+        ref += v
+    got = out.view(16, 256).double().cpu()
+    assert torch.allclose(got, ref.expand(16, 256), rtol=1e-5, atol=1e-5)
