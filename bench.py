@@ -269,6 +269,16 @@ def leg_accuracy(ss, h, mm, D, suns, c):
              "tests_per_ray": sum(k[0] for k in cnt) / rays,
              "samples_per_ray": sum(k[1] for k in cnt) / rays,
              "launch_ms": t_ex}
+    # the same 8 suns as one persistent batched launch (tap-bound pyramid and max-mip
+    # rebuilt inside the call), outputs checked against the per-sun launches
+    outs_b = [torch.empty_like(h) for _ in suns]
+    ss.shadow_cast_batched([h], [D], suns, px, outs=[outs_b], mms=[mm], bounds=[bound])
+    t_b = min(_timed(lambda: ss.shadow_cast_batched([h], [D], suns, px, outs=[outs_b], mms=[mm],
+                                                     bounds=[bound]), 2))
+    exact["batched_mrays_s"] = rays / (t_b / 1e3) / 1e6
+    exact["batched_equal_per_sun"] = all(torch.equal(outs_b[k].view(torch.int32),
+                                                     ex[k].view(torch.int32)) for k in range(len(suns)))
+    del outs_b
     desc = _err_stats(dp, u2)
     point = _err_stats(pt, u2)
     uni1 = _err_stats(u1, u2)

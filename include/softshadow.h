@@ -68,7 +68,11 @@ typedef struct {
   double max_len_m;        /* horizontal ray cap; <= 0: rays run to the tile edge */
   int32_t n_prime0;        /* levels of the first segment, N'_0 (Sec. 3.2; 0 -> 5) */
   int32_t schedule;        /* SS_SCHED_* (Sec. 3.3 interval concatenation) */
-  int32_t n_segments;      /* > 0 fixes the number of concatenated runs; 0: reach max_len_m */
+  int32_t n_segments;      /* > 0 fixes the number of concatenated runs; 0: reach max_len_m.
+                              At most 48 runs: a run spans at most the tile's top mip level
+                              (2^(L-1) texels), so a cap far longer than the tile (e.g. 2 km
+                              on a 16-texel tile) is SS_ERR_UNSUPPORTED; rays stop at the tile
+                              edge anyway, so such tiles take a cap <= their extent or none */
   int32_t mode;            /* SS_MODE_* */
   double uniform_step;     /* SS_MODE_UNIFORM: step in texels of horizontal travel, >= 1/64 (0 -> 1) */
   int32_t prune;           /* 1: skip work that cannot change the result (bitwise-identical) */

@@ -51,13 +51,14 @@ __device__ __forceinline__ int resolve_claim(const long long* __restrict__ item_
   return -1;
 }
 
-// The stepping modes are held to 8 wavefronts per SIMD (at most 64 VGPRs; the
-// compiler spills a dword or two, outside the per-run loops): 5% faster on the 4096^2
-// x 8-sun workload than the 7 its free allocation gives.  The exact mode keeps
-// its registers.
+// Occupancy: the stepping modes are held to 8 wavefronts per SIMD (at most 64
+// VGPRs; the compiler spills a dword or two, outside the per-run loops), 5%
+// faster on the 4096^2 x 8-sun workload than the 7 their free allocation
+// gives; the exact mode to 7 (72 VGPRs, no spill), 6% faster than its free 6
+// and than 8 (which spills inside the walk).
 template <bool SPHERE, int TW, int MODE>
 __global__ __attribute__((amdgpu_flat_work_group_size(256, 256),
-                          amdgpu_waves_per_eu(MODE == SS_MODE_EXACT ? 1 : 8))) void batched_kernel(const TileK* __restrict__ pairs,
+                          amdgpu_waves_per_eu(MODE == SS_MODE_EXACT ? 7 : 8))) void batched_kernel(const TileK* __restrict__ pairs,
                                                       float* const* __restrict__ outs,
                                                       const long long* __restrict__ item_start,
                                                       const long long* __restrict__ xstart,

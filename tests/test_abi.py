@@ -313,3 +313,14 @@ def test_valu_probe_validation(L):
     lib = L.lib()
     for args in [(0, 8, 0x400000), (16, 0, 0x400000), (16, 1 << 31, 0x400000), (16, 8, None)]:
         assert lib.ss_probe_valu(*args, None) == L.SS_ERR_INVALID_ARG, args
+
+
+def test_cap_far_beyond_a_small_tile_is_unsupported(L):
+    """A run spans at most the tile's top mip level, so a cap of many tile widths needs more
+    than the 48 runs a ray may take: rejected before anything is enqueued."""
+    t, s, p = good(L)  # 64 x 64 texels of 10 m
+    p.max_len_m = 100000.0
+    assert cast(L, t, s, p) == L.SS_ERR_UNSUPPORTED
+    p.max_len_m = 640.0
+    t.height = 0  # a call that gets past the schedule fails on the missing buffer instead
+    assert cast(L, t, s, p) == L.SS_ERR_INVALID_ARG

@@ -64,6 +64,30 @@ def test_batched_equals_per_tile(ss, mode):
 
 
 @pytest.mark.parametrize("mode", [0, 2])
+def test_tiny_tiles_and_empty_bands(ss, mode):
+    """Tiles of one to a few ray blocks (most of a pair's 8 per-XCD bands are empty) mixed
+    with a larger one: every pair's output equals the per-tile kernel's bit for bit."""
+    from synth import make_dem
+    shapes = [(1, 1, 20.0), (5, 3, 20.0), (16, 16, 10.0), (17, 40, 12.0), (33, 9, 15.0),
+              (200, 150, 10.0)]
+    hs = [make_dem(w, r, D, 300.0, 90 + k, craters=2, device=dev())
+          for k, (w, r, D) in enumerate(shapes)]
+    texels = [D for _, _, D in shapes]
+    suns = [(math.radians(0.8 + 0.9 * k), 0.4 + 1.7 * k, math.radians(0.267)) for k in range(3)]
+    # no cap: rays run to the tile edge (a cap far beyond a tiny tile needs more runs than
+    # the library allows)
+    params = ss.Params(radius_m=R, max_len_m=0.0, mode=mode)
+    ref = per_tile(ss, hs, texels, suns, params)
+    for tile in (1, 3):
+        params.ray_tile = tile
+        got = ss.shadow_cast_batched(hs, texels, suns, params)
+        torch.cuda.synchronize()
+        for t in range(len(hs)):
+            for k in range(len(suns)):
+                assert same(got[t][k], ref[t][k]), (mode, tile, t, k)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
 def test_graph_plan_replays(ss, mode):
     hs, texels, suns = small_batch()
     params = ss.Params(radius_m=R, max_len_m=2500.0, mode=mode)
