@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -203,9 +204,28 @@ static int32_t check_sun(const ss_sun* s) {
   return SS_OK;
 }
 
+// Workgroups of 256 lanes one device holds at once (8 per CU at 8 wavefronts
+// per SIMD): the per-tile kernels remap workgroup ids within groups of this
+// many.  Cached per device.
+static int device_wg_group() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 2048;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 256;
+  v = 8 * ncu;
+  cache[dev].store(v, std::memory_order_relaxed);
+  return v;
+}
+
 static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp, double max_len_m,
                           double radius, TileK* K) {
   memset(K, 0, sizeof(*K));
+  K->wg_group = device_wg_group();
   const int W = t->width, H = t->rows;
   const int L = levels_of(W, H);
   if (L > SS_MAXLEV) return SS_ERR_UNSUPPORTED;

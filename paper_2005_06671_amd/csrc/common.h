@@ -35,7 +35,8 @@ struct TileK {
   float tau[SS_MAXSEG + 1];  // ray length where run j starts (tau[nseg] = end)
   int a0[SS_MAXSEG];         // grid index of run j's start: tau_j = (a0_j + 1) delta/2
   int prune;                 // 1: result-invariant early exits enabled
-  int pad_;
+  int wg_group;              // per-tile kernels: workgroup ids are remapped within groups of
+                             // this many (one device-full, a multiple of 8)
 };
 
 // Ray tile shapes: lanes of one wavefront cover TW x TH texels (TW * TH = 64),

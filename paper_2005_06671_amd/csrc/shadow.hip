@@ -2,9 +2,14 @@
 // its instrumented twin, and the adjoint.
 //
 // One lane = one ray (texel centre); one wavefront = a TW x TH ray tile; a
-// 256-thread workgroup = 2 x 2 wavefront tiles.  Workgroup ids are remapped
-// so each XCD (ids are dealt round-robin over the 8 XCDs) works on one
-// contiguous band of the tile and its rays reuse that XCD's L2.
+// 256-thread workgroup = 2 x 2 wavefront tiles.  Workgroup ids are dealt
+// round-robin over the 8 XCDs and run roughly in order, about one device-full
+// at a time.  They are remapped within groups of one device-full (T.wg_group
+// ids): inside a group each XCD takes one contiguous run of ray blocks, so the
+// XCDs work side by side on one slab of the tile with their rays' neighbours in
+// their own L2.  One contiguous band of the whole tile per XCD kept the same
+// locality but left the XCDs with unequal work (the slowest band set the
+// launch time): on the 4096^2 tile's 8 suns the groups are 18% faster.
 #include "kernels.h"
 #include "ray.h"
 
@@ -13,6 +18,13 @@ namespace ss {
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   const int per = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
   return x * per + min(x, rem) + k;
+}
+
+// xcd_remap inside each group of grp ids (grp a multiple of 8, so an id keeps
+// its XCD): a bijection of [0, nb).
+__device__ __forceinline__ int xcd_remap_grouped(int b, int nb, int grp) {
+  const int lo = (b / grp) * grp;
+  return lo + xcd_remap(b - lo, min(grp, nb - lo));
 }
 
 __device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
@@ -38,8 +50,8 @@ __device__ __forceinline__ void coords_of(int b, int nbx, int& i, int& j) {
 }
 
 template <int TW>
-__device__ __forceinline__ void ray_coords(int nbx, int nblocks, int& i, int& j) {
-  coords_of<TW>(xcd_remap((int)blockIdx.x, nblocks), nbx, i, j);
+__device__ __forceinline__ void ray_coords(int nbx, int nblocks, int grp, int& i, int& j) {
+  coords_of<TW>(xcd_remap_grouped((int)blockIdx.x, nblocks, grp), nbx, i, j);
 }
 
 // FLAGS: FWD_COUNT adds the work units to counter[0..1]; FWD_SAVE writes each
@@ -58,7 +70,7 @@ __global__ __launch_bounds__(256) void shadow_kernel(TileK T, float* __restrict_
     __syncthreads();
   }
   int li, lj;
-  ray_coords<TW>(nbx, nblocks, li, lj);
+  ray_coords<TW>(nbx, nblocks, T.wg_group, li, lj);
   unsigned n_lb = 0, n_smp = 0;
   if (li < T.RW && lj < T.RH) {
     const int i = T.rx0 + li, j = T.ry0 + lj;
@@ -267,7 +279,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
     __syncthreads();
   }
   double ge = 0.0, ga = 0.0;
-  const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int b = xcd_remap_grouped((int)blockIdx.x, (int)gridDim.x, T.wg_group);
   for (int g = 0; g < AdjBlocks<SAVED>::n; ++g) {
     const int vb = b * AdjBlocks<SAVED>::n + g;
     if (vb >= nblocks) break;
