@@ -191,7 +191,7 @@ def summarize_counters(csv_path, out_dir):
     with open(os.path.join(out_dir, COUNTERS_FILE), "w") as f:
         f.write("# rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU "
                 "SQ_INSTS_VALU_TRANS_F32 TCC_HIT_sum TCC_MISS_sum --kernel-include-regex "
-                "'batched_kernel|shadow_kernel' --output-format csv -d <dir> -o bench -- python "
+                "'flat_kernel|batched_kernel|shadow_kernel' --output-format csv -d <dir> -o bench -- python "
                 "bench.py --steps 1 --warmup 0 --no-cpu --no-extras --dem-cache /tmp/dem_tile.npy\n")
         f.write("\n".join(lines) + "\n")
 
@@ -806,7 +806,7 @@ def main():
                                     for k in range(len(suns))],
               "batched_plan": {
                   "ms_per_step": b_ms, "mrays_s": rays_per_step / (b_ms / 1e3) / 1e6,
-                  "kernel": "batched_kernel<descent> (one persistent launch over the 8 suns)",
+                  "kernel": "flat_kernel<descent> (one launch over every ray block of the 8 suns)",
                   "graph_replay_ms": b_launch,
                   "roofline_frac": ops_per_launch * len(suns) / (b_launch / 1e3) / 1e12
                                    / PEAK_VALU_TOPS,

@@ -307,9 +307,13 @@ int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns);
 
 /* Builds every tile's maximum mipmap, then computes d_shadow[t*n_suns + k]
  * (host array of device pointers, each [rows_t][width_t]) for tile t and sun
- * k in one persistent launch that takes (tile, sun, ray block) items from a
- * queue in d_workspace.  Outputs are bit-identical to ss_shadow_cast with the
- * same parameters.  d_workspace is used for the duration of the call.
+ * k in one launch over every (tile, sun, ray block): by default one workgroup
+ * per ray block of every pair, or, with the environment variable
+ * SS_BATCH_FORM=persistent (and always for batches of 2^31 ray blocks or
+ * more), a persistent kernel whose workgroups take ray blocks from per-XCD
+ * queues in d_workspace.  Outputs are bit-identical to ss_shadow_cast with the
+ * same parameters in either form.  d_workspace is used for the duration of
+ * the call.
  * Every mode; SS_MODE_EXACT needs each tile's `bound` buffer, which the call
  * (and a plan's graph) rebuilds from the heights like the maximum mipmap. */
 int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
@@ -319,10 +323,10 @@ int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_s
 /* A captured HIP graph of the batched call for fixed buffers.  Create picks the
  * ray-tile shape and mipmap fusion depth by timing the candidates on these
  * inputs (it synchronises `stream` while tuning), then captures the maxmip
- * builds and the persistent launch.  Launch replays the graph on `stream`; the
+ * builds and the batched launch (in the form SS_BATCH_FORM selects).  Launch replays the graph on `stream`; the
  * workspace belongs to the plan until it is destroyed.  Choices are kept per
  * process, keyed by the device architecture, the tile sizes and spacings, the
- * sun count and the method parameters; with the environment variable
+ * sun count, the method parameters and the form; with the environment variable
  * SS_TUNE_CACHE naming a file they also persist across processes (read once,
  * new choices appended as JSON lines {"key": ..., "ray_tile": n,
  * "fuse_depth": f}).  The choices never change results. */

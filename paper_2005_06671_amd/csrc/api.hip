@@ -702,6 +702,15 @@ static void* g_stage = nullptr;
 static size_t g_stage_cap = 0;
 static hipEvent_t g_stage_ev = nullptr;
 
+// The batched call's form: flat (one workgroup per ray block of every pair;
+// the default) or, with SS_BATCH_FORM=persistent in the environment, the
+// persistent kernel with per-XCD queues.  Batches of 2^31 blocks or more always
+// take the persistent form.  Both give the same outputs bit for bit.
+static bool batch_persistent() {
+  const char* e = getenv("SS_BATCH_FORM");
+  return e && strcmp(e, "persistent") == 0;
+}
+
 static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchTables& bt,
                              unsigned char* ws, int fuse, int n_wg, hipStream_t stream) {
   WsLayout L;
@@ -715,6 +724,14 @@ static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchT
         (rc = ss_bound_build(tiles[t].height, tiles[t].width, tiles[t].rows,
                              const_cast<float*>(tiles[t].bound), stream)))
       return rc;
+  }
+  if (!batch_persistent() && bt.bd.total_items < (1LL << 31)) {
+    SS_HIP(launch_batched_flat(reinterpret_cast<const TileK*>(ws + L.pairs),
+                               reinterpret_cast<float* const*>(ws + L.outs),
+                               reinterpret_cast<const long long*>(ws + L.start),
+                               reinterpret_cast<const int*>(ws + L.nbx), bt.bd, device_wg_group(),
+                               bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile, stream));
+    return SS_OK;
   }
   SS_HIP(launch_fill_u32(reinterpret_cast<unsigned int*>(ws + L.counter), 0u, SS_NXCD, stream));
   SS_HIP(launch_batched(reinterpret_cast<const TileK*>(ws + L.pairs),
@@ -824,7 +841,7 @@ static std::string tune_key(const ss_tile* tiles, int n_tiles, int n_suns, const
     snprintf(buf, sizeof buf, "%dx%d@%.4g,", tiles[t].width, tiles[t].rows, tiles[t].texel_m);
     k += buf;
   }
-  snprintf(buf, sizeof buf, "|%d", n_suns);
+  snprintf(buf, sizeof buf, "|%d|%s", n_suns, batch_persistent() ? "persistent" : "flat");
   return k + buf;
 }
 

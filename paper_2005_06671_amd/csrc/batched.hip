@@ -131,6 +131,91 @@ __global__ __attribute__((amdgpu_flat_work_group_size(256, 256),
   }
 }
 
+// Flat form: one workgroup per ray block of every pair (grid = all blocks),
+// ids remapped as the per-tile kernels remap theirs (groups of one device-full,
+// TileK.wg_group, a run per XCD inside each); the pair comes from the block
+// prefix sums.  No queue: the hardware deals the workgroups, and the batch
+// still ends with one tail.
+static_assert(SS_ITEM_BLOCKS == 1, "the flat form reads the item prefix sums as block prefix sums");
+
+template <bool SPHERE, int TW, int MODE>
+__global__ __launch_bounds__(256) void flat_kernel(const TileK* __restrict__ pairs,
+                                                   float* const* __restrict__ outs,
+                                                   const long long* __restrict__ block_start,
+                                                   const int* __restrict__ pair_nbx, int n_pairs,
+                                                   int n_blocks, int grp) {
+  constexpr int TH = 64 / TW;
+  __shared__ int tab[SS_MAXLEV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long blk_all = xcd_remap_grouped((int)blockIdx.x, n_blocks, grp);
+  const int pair = __builtin_amdgcn_readfirstlane(pair_of(block_start, n_pairs, blk_all));
+  const TileK& T = pairs[pair];
+  if (MODE == SS_MODE_EXACT) {
+    bound_tab_fill(T, tab);
+    __syncthreads();
+  }
+  const int nbx = pair_nbx[pair];
+  const long long blk = blk_all - block_start[pair];
+  const int bxi = (int)(blk % nbx), byi = (int)(blk / nbx);
+  const int li = bxi * (2 * TW) + (wave & 1) * TW + lane % TW;
+  const int lj = byi * (2 * TH) + (wave >> 1) * TH + lane / TW;
+  if (li < T.RW && lj < T.RH) {
+    const int i = T.rx0 + li, j = T.ry0 + lj;
+    const float hp = T.h[j * T.W + i];
+    Ray<SPHERE> r;
+    ray_init(T, i, j, hp, r);
+    unsigned n_lb = 0, n_smp = 0;
+    const float alpha = trace_ray<SPHERE, MODE>(T, r, n_lb, n_smp, tab).alpha;
+    outs[pair][lj * T.RW + li] = disc_fraction(alpha, T);
+  }
+}
+
+template <bool SPHERE, int MODE>
+static hipError_t launch_flat_m(const TileK* a, float* const* b, const long long* c, const int* d,
+                                int n_pairs, int n_blocks, int grp, int ray_tile, hipStream_t s) {
+  const dim3 g((unsigned)n_blocks), t(256);
+  switch (ray_tile) {
+    case SS_TILE_16x4:
+      hipLaunchKernelGGL((flat_kernel<SPHERE, 16, MODE>), g, t, 0, s, a, b, c, d, n_pairs, n_blocks, grp);
+      break;
+    case SS_TILE_4x16:
+      hipLaunchKernelGGL((flat_kernel<SPHERE, 4, MODE>), g, t, 0, s, a, b, c, d, n_pairs, n_blocks, grp);
+      break;
+    case SS_TILE_32x2:
+      hipLaunchKernelGGL((flat_kernel<SPHERE, 32, MODE>), g, t, 0, s, a, b, c, d, n_pairs, n_blocks, grp);
+      break;
+    default:
+      hipLaunchKernelGGL((flat_kernel<SPHERE, 8, MODE>), g, t, 0, s, a, b, c, d, n_pairs, n_blocks, grp);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <bool SPHERE>
+static hipError_t launch_flat_s(const TileK* a, float* const* b, const long long* c, const int* d,
+                                int n_pairs, int n_blocks, int grp, int mode, int ray_tile,
+                                hipStream_t s) {
+  switch (mode) {
+    case SS_MODE_UNIFORM: return launch_flat_m<SPHERE, SS_MODE_UNIFORM>(a, b, c, d, n_pairs, n_blocks, grp, ray_tile, s);
+    case SS_MODE_POINT: return launch_flat_m<SPHERE, SS_MODE_POINT>(a, b, c, d, n_pairs, n_blocks, grp, ray_tile, s);
+    case SS_MODE_EXACT: return launch_flat_m<SPHERE, SS_MODE_EXACT>(a, b, c, d, n_pairs, n_blocks, grp, ray_tile, s);
+    default: return launch_flat_m<SPHERE, SS_MODE_DP>(a, b, c, d, n_pairs, n_blocks, grp, ray_tile, s);
+  }
+}
+
+hipError_t launch_batched_flat(const TileK* d_pairs, float* const* d_out_ptrs,
+                               const long long* d_block_start, const int* d_pair_nbx,
+                               const BatchDesc& bd, int grp, bool sphere, int mode, int ray_tile,
+                               hipStream_t stream) {
+  if (bd.total_items <= 0) return hipSuccess;
+  const int nb = (int)bd.total_items;
+  if (sphere)
+    return launch_flat_s<true>(d_pairs, d_out_ptrs, d_block_start, d_pair_nbx, bd.n_pairs, nb,
+                               grp, mode, ray_tile, stream);
+  return launch_flat_s<false>(d_pairs, d_out_ptrs, d_block_start, d_pair_nbx, bd.n_pairs, nb, grp,
+                              mode, ray_tile, stream);
+}
+
 __global__ void fill_u32_kernel(unsigned int* p, unsigned int v, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;

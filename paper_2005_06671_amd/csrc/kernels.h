@@ -48,6 +48,12 @@ hipError_t launch_batched(const TileK* d_pairs, float* const* d_out_ptrs, const 
                           const long long* d_xstart, const int* d_pair_nbx, unsigned int* d_counter,
                           const BatchDesc& bd, bool sphere, int mode, int ray_tile, int n_workgroups,
                           hipStream_t stream);
+// Flat form of the batched call: one workgroup per ray block of every pair
+// (n blocks = bd.total_items with one block per item, below 2^31).
+hipError_t launch_batched_flat(const TileK* d_pairs, float* const* d_out_ptrs,
+                               const long long* d_block_start, const int* d_pair_nbx,
+                               const BatchDesc& bd, int grp, bool sphere, int mode, int ray_tile,
+                               hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream);
 int batched_workgroups(bool sphere, int mode, int ray_tile);
 

@@ -16,6 +16,20 @@
 
 #define SS_INF __builtin_inff()
 
+// Workgroup ids are dealt round-robin over the 8 XCDs.  xcd_remap gives each
+// XCD one contiguous run of [0, nb) (the first nb % 8 XCDs one id more);
+// xcd_remap_grouped does so inside each group of grp ids (grp a multiple of 8,
+// so an id keeps its XCD).  Both are bijections of [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+  return x * per + min(x, rem) + k;
+}
+
+__device__ __forceinline__ int xcd_remap_grouped(int b, int nb, int grp) {
+  const int lo = (b / grp) * grp;
+  return lo + xcd_remap(b - lo, min(grp, nb - lo));
+}
+
 __device__ __forceinline__ float ss_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float ss_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 

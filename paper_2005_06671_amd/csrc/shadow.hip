@@ -15,17 +15,6 @@
 
 namespace ss {
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int per = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
-  return x * per + min(x, rem) + k;
-}
-
-// xcd_remap inside each group of grp ids (grp a multiple of 8, so an id keeps
-// its XCD): a bijection of [0, nb).
-__device__ __forceinline__ int xcd_remap_grouped(int b, int nb, int grp) {
-  const int lo = (b / grp) * grp;
-  return lo + xcd_remap(b - lo, min(grp, nb - lo));
-}
 
 __device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
 #pragma unroll

@@ -1,4 +1,4 @@
-"""Batched form: one persistent launch over (tile, sun, ray block) items and its
+"""Batched form: one launch over (tile, sun, ray block) items (flat or persistent) and its
 captured HIP graph.  Outputs must be bit-identical to the per-tile kernel, on
 replays too, and within 1e-4 of the oracle on sampled rays of the full
 8-tile x 64-sun workload."""
@@ -49,8 +49,18 @@ def same(a, b):
     return torch.equal(a.view(torch.int32), b.view(torch.int32))
 
 
+@pytest.fixture(params=["flat", "persistent"])
+def form(request, monkeypatch):
+    """The batched call's two forms (SS_BATCH_FORM); outputs must not depend on it."""
+    if request.param == "persistent":
+        monkeypatch.setenv("SS_BATCH_FORM", "persistent")
+    else:
+        monkeypatch.delenv("SS_BATCH_FORM", raising=False)
+    return request.param
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
-def test_batched_equals_per_tile(ss, mode):
+def test_batched_equals_per_tile(ss, mode, form):
     hs, texels, suns = small_batch()
     params = ss.Params(radius_m=R, max_len_m=2500.0, mode=mode)
     ref = per_tile(ss, hs, texels, suns, params)
@@ -64,7 +74,7 @@ def test_batched_equals_per_tile(ss, mode):
 
 
 @pytest.mark.parametrize("mode", [0, 2])
-def test_tiny_tiles_and_empty_bands(ss, mode):
+def test_tiny_tiles_and_empty_bands(ss, mode, form):
     """Tiles of one to a few ray blocks (most of a pair's 8 per-XCD bands are empty) mixed
     with a larger one: every pair's output equals the per-tile kernel's bit for bit."""
     from synth import make_dem
@@ -88,7 +98,7 @@ def test_tiny_tiles_and_empty_bands(ss, mode):
 
 
 @pytest.mark.parametrize("mode", [0, 2])
-def test_graph_plan_replays(ss, mode):
+def test_graph_plan_replays(ss, mode, form):
     hs, texels, suns = small_batch()
     params = ss.Params(radius_m=R, max_len_m=2500.0, mode=mode)
     ref = per_tile(ss, hs, texels, suns, params)
