@@ -461,8 +461,8 @@ def leg_frame(ss, reps=10):
     shadow ray from every visible point (shaded in 8 x 8 pixel tiles), in each shadow mode.
     Per image size: view
     rays by the pyramid walk and by the dense march (identical output), grid samples
-    and pyramid cells per pixel, shadow rays per mode, and the frame time and rate
-    (view walk + shadows).  Terrain set-up (max-mip, tap-bound pyramid) runs once per
+    and pyramid cells per pixel, shadow rays per mode, the frame time and rate (view
+    walk + shadows), and the adjoint of the descent's shadow rays at the hits.  Terrain set-up (max-mip, tap-bound pyramid) runs once per
     terrain change, not per frame, and is reported apart."""
     import torch
     from synth import config, dem_for, sun_list, R_MOON
@@ -511,6 +511,17 @@ def leg_frame(ss, reps=10):
             res[f"shadow_{name}_ms"] = ms
             res[f"frame_{name}_ms"] = vh + ms
             res[f"frame_{name}_hz"] = 1e3 / (vh + ms)
+        # the adjoint at the frame's hits (points held fixed): dL/dh and dL/d(sun) for a
+        # seeded upstream gradient over the visible pixels
+        g = torch.randn((ph, pw), generator=torch.Generator().manual_seed(11)).to(h.device)
+        g = torch.where(torch.isfinite(t), g, torch.zeros_like(g)).contiguous()
+        gh = torch.zeros_like(h)
+        gsun = torch.zeros(2, dtype=torch.float64, device=h.device)
+        pd = modes["descent"]
+        ss.shadow_points_backward(h, D, e, a, xy, g, r, pd, mm=mm, grad_h=gh, grad_sun=gsun)
+        res["shadow_adjoint_descent_ms"] = min(_timed(
+            lambda: ss.shadow_points_backward(h, D, e, a, xy, g, r, pd, mm=mm, grad_h=gh,
+                                              grad_sun=gsun), reps))
         out[f"{pw}x{ph}"] = res
     out["paper_context"] = ("GTX 970M, whole frame with shading: 1920x1080 5.4 ms (185 Hz) "
                             "{5,5,5}, 6.2 ms {5,5,5,3}, 18.2 ms uniform 100 steps; 512^2 402 Hz")
