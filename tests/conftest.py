@@ -18,3 +18,13 @@ def orc():
     import oracle
     oracle.load()
     return oracle
+
+
+@pytest.fixture(params=["flat", "persistent"])
+def form(request, monkeypatch):
+    """The batched call's two forms (SS_BATCH_FORM); outputs must not depend on it."""
+    if request.param == "persistent":
+        monkeypatch.setenv("SS_BATCH_FORM", "persistent")
+    else:
+        monkeypatch.delenv("SS_BATCH_FORM", raising=False)
+    return request.param

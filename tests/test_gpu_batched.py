@@ -49,16 +49,6 @@ def same(a, b):
     return torch.equal(a.view(torch.int32), b.view(torch.int32))
 
 
-@pytest.fixture(params=["flat", "persistent"])
-def form(request, monkeypatch):
-    """The batched call's two forms (SS_BATCH_FORM); outputs must not depend on it."""
-    if request.param == "persistent":
-        monkeypatch.setenv("SS_BATCH_FORM", "persistent")
-    else:
-        monkeypatch.delenv("SS_BATCH_FORM", raising=False)
-    return request.param
-
-
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_batched_equals_per_tile(ss, mode, form):
     hs, texels, suns = small_batch()

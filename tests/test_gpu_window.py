@@ -102,7 +102,7 @@ def test_window_adjoint(ss):
     assert torch.allclose(gs_w, gs_f, rtol=1e-6, atol=1e-12)
 
 
-def test_batched_windows(ss):
+def test_batched_windows(ss, form):
     hs = [torch.from_numpy(rough(s, s[0], 100.0)).cuda() for s in [(96, 128), (136, 200)]]
     texels = [20.0, 10.0]
     wins = [(5, 7, 100, 50), None]
