@@ -32,5 +32,5 @@ def test_committed_traffic_record_is_well_formed():
     with open(os.path.join(ROOT, "profiles", "descent_tile_traffic.json")) as f:
         d = json.load(f)
     assert len(d["kernel_src_sha"]) == 16 and d["hbm_bytes_per_launch"] > 0
-    assert "shadow_kernel<true, 8, 0, 0>" in d["kernel"]
+    assert "flat_kernel<true, 8, 0>" in d["kernel"]
     assert d["fetch_scale"] > 0 and d["write_scale"] > 0 and "rocprofv3" in d["command"]
