@@ -649,7 +649,8 @@ def shadow_cast_batched(heights, texels, suns, params: Params | None = None, out
     of its ray window).
 
     Builds every tile's mipmap (and, in the exact mode, its tap-bound pyramid
-    into ``bounds``) and runs one persistent launch over all items.
+    into ``bounds``) and runs one launch over every ray block of every (tile, sun)
+    (flat by default; SS_BATCH_FORM=persistent selects the persistent form).
     """
     params = params or Params()
     if len(heights) == 0 or len(suns) == 0:

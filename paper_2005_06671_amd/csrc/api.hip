@@ -896,8 +896,8 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
       }
     }
   }
-  // ray-tile shape: the persistent kernel over (largest tile) x (sun subset); the
-  // sub-batch's workspace fits in the caller's (fewer pairs)
+  // ray-tile shape: the batched launch (in the selected form) over (largest tile) x
+  // (sun subset); the sub-batch's workspace fits in the caller's (fewer pairs)
   const int ns = n_suns < 8 ? n_suns : 8;
   std::vector<ss_sun> sub(ns);
   std::vector<float*> sub_out(ns);
