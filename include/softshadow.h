@@ -18,7 +18,10 @@
  *    the call only.
  *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
  *    work on it: they return before the GPU finishes and never synchronise the
- *    device, except where a function says otherwise.
+ *    device, except where a function says otherwise.  Apart from
+ *    ss_batched_plan_create, every call that takes a stream only launches
+ *    kernels on it (no allocation, no host wait, no memset or copy node), so
+ *    it may be recorded into a caller's HIP graph by stream capture.
  *  - Return value: SS_OK (0) or a negative SS_ERR_* status; arguments are
  *    validated on the host before anything is enqueued, so an error leaves
  *    every output untouched.  No C++ exception crosses the ABI.
@@ -83,7 +86,8 @@ typedef struct {
 /* One heightfield tile.  `maxmip` holds levels >= 1 of its maximum mipmap in
  * the packed layout below (built by ss_maxmip_build); `bound` holds its
  * tap-bound pyramid (built by ss_bound_build), read by SS_MODE_EXACT only and
- * may be NULL otherwise.
+ * may be NULL otherwise.  The per-tile calls only read both; the batched call
+ * and a plan's graph (re)build them from `height`, so they are not const.
  *
  * Ray window: rays start only at texels (i, j) with ray_x0 <= i < ray_x0 +
  * ray_w and ray_y0 <= j < ray_y0 + ray_h, while they see the whole tile.  A
@@ -95,10 +99,10 @@ typedef struct {
  * the tile. */
 typedef struct {
   const float* height;     /* device, [rows][width] */
-  const float* maxmip;     /* device, ss_maxmip_floats(width, rows) floats */
+  float* maxmip;           /* device, ss_maxmip_floats(width, rows) floats */
   int32_t width, rows;     /* >= 1 */
   double texel_m;          /* > 0 */
-  const float* bound;      /* device, ss_bound_floats(width, rows) floats, or NULL */
+  float* bound;            /* device, ss_bound_floats(width, rows) floats, or NULL */
   int32_t ray_x0, ray_y0, ray_w, ray_h;  /* ray window, all 0 = whole tile */
 } ss_tile;
 
@@ -305,15 +309,18 @@ int32_t ss_shadow_cast_backward_saved(const ss_tile* tile, const ss_sun* sun,
 /* Bytes of device workspace ss_shadow_cast_batched needs (-1: bad sizes). */
 int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns);
 
-/* Builds every tile's maximum mipmap, then computes d_shadow[t*n_suns + k]
+/* Builds every tile's maximum mipmap (written to tiles[t].maxmip), then
+ * computes d_shadow[t*n_suns + k]
  * (host array of device pointers, each [rows_t][width_t]) for tile t and sun
  * k in one launch over every (tile, sun, ray block): by default one workgroup
  * per ray block of every pair, or, with the environment variable
  * SS_BATCH_FORM=persistent (and always for batches of 2^31 ray blocks or
  * more), a persistent kernel whose workgroups take ray blocks from per-XCD
  * queues in d_workspace.  Outputs are bit-identical to ss_shadow_cast with the
- * same parameters in either form.  d_workspace is used for the duration of
- * the call.
+ * same parameters in either form.  d_workspace (256-byte aligned) is used by
+ * the work this call enqueues; the per-pair set-up reaches it through kernel
+ * arguments, so the call allocates nothing, never waits on the device and may
+ * be captured into a caller's HIP graph (a replay redoes the whole call).
  * Every mode; SS_MODE_EXACT needs each tile's `bound` buffer, which the call
  * (and a plan's graph) rebuilds from the heights like the maximum mipmap. */
 int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,

@@ -1,4 +1,5 @@
-/* Valid results of the descent under near-ties (test infrastructure).
+/* Valid results of the descent (and of uniform stepping) under near-ties
+ * (test infrastructure).
  *
  * The descent takes discrete decisions: which texels the ray crosses, which of
  * them has the smallest lower bound, where the half-texel samples sit, which
@@ -394,10 +395,53 @@ static void segment_alternatives(alt_t* A, int jseg, valset* out) {
   }
 }
 
+/* Uniform stepping (Sec. 2, Fig. 1b; Sec. 6.3) takes one kind of discrete
+ * decision: which steps count, i.e. lie inside the tile and within the cap.
+ * A step whose position is within the position tolerance of the tile edge, or
+ * whose length is within it of the cap, may count or not (a step just outside
+ * is evaluated at the clamped edge if taken); every other step counts exactly
+ * as in the plain loop.  The minimum over the steps that surely count is a
+ * valid result, and so is each optional step's clearance below it (a subset of
+ * the optional steps yields the smallest of them, or the sure minimum). */
+static void uniform_alternatives(alt_t* A, double du, valset* out) {
+  const ray_t* r = A->r;
+  const setup_t* s = r->s;
+  const double W = s->p->width, H = s->p->rows;
+  double sure = INFINITY;
+  valset opt;
+  opt.n = 0;
+  for (long k = 0;; ++k) {
+    if (--A->budget < 0) {
+      A->overflow = 1;
+      return;
+    }
+    const double t = s->tau0 + (double)k * du;
+    const double e = eps_t(A, t);
+    const double ecap = e * s->delta;
+    double qx, qy, Ht;
+    or_ray_point(r, t, &qx, &qy, &Ht);
+    const double dmin = fmin(fmin(qx, W - qx), fmin(qy, H - qy));
+    const int cap_opt = ecap > 0.0 && fabs(t - s->tcap_uniform) <= ecap;
+    const int edge_opt = e > 0.0 && fabs(dmin) < e;
+    if (t > s->tcap_uniform && !cap_opt) break;
+    if (!or_inside(s, qx, qy) && !edge_opt) break;
+    const double dh = Ht - or_bilinear(s, qx < 0 ? 0 : (qx >= W ? W - 1e-9 : qx),
+                                       qy < 0 ? 0 : (qy >= H ? H - 1e-9 : qy));
+    const double a = or_alpha_of(r, t, dh);
+    if (cap_opt || edge_opt)
+      vs_add(A, &opt, a);
+    else if (a < sure)
+      sure = a;
+  }
+  vs_add(A, out, sure);
+  for (int k = 0; k < opt.n; ++k)
+    if (opt.v[k] < sure) vs_add(A, out, opt.v[k]);
+}
+
 int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray, double eh_abs,
                         double eh_rel, double et_abs, double et_rel, double* alpha_out,
                         int32_t max_out) {
-  if (!c || !p || p->mode != 0) return -2;
+  if (!c || !p || p->mode < 0 || p->mode > 2) return -2;
   if (ray < 0 || ray >= (int64_t)c->W * c->H) return -2;
   setup_t s;
   or_setup(&s, c, p);
@@ -411,6 +455,18 @@ int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray, double
   A.et_rel = et_rel;
   A.budget = 200000;
   A.overflow = 0;
+  if (p->mode != 0) {
+    /* uniform stepping (mode 1) and the exact mode, defined as the minimum over
+     * the half-texel grid (mode 2) */
+    valset res;
+    res.n = 0;
+    A.budget = 4000000;
+    uniform_alternatives(&A, p->mode == 1 ? p->uniform_step * s.delta : 0.5 * s.delta, &res);
+    if (A.overflow) return -1;
+    int n = res.n < max_out ? res.n : max_out;
+    for (int k = 0; k < n; ++k) alpha_out[k] = res.v[k];
+    return n;
+  }
   static __thread valset segs[OR_MAXSEG];
   for (int j = 0; j < s.nseg; ++j) {
     segs[j].n = 0;

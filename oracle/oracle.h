@@ -85,8 +85,11 @@ int32_t or_shadow(const or_ctx* c, const or_params* p, const int64_t* rays, int6
  * whose FP64 margin is below a tolerance may go either way.  Height margins
  * (lower bounds, final clearances) use eh_abs + eh_rel * t metres, positions
  * (crossings, rounding, tile edge) et_abs + et_rel * t/delta texels, t the
- * ray length there.  Returns the number of values written (<= max_out), or -1
- * when the branch cap was exceeded. */
+ * ray length there.  Modes 0 (descent), 1 (uniform stepping) and 2 (the
+ * minimum over the half-texel grid); for the last two the only decisions are
+ * whether a step lies inside the tile and within the cap.  Returns the number
+ * of values written (<= max_out), -1 when the branch cap was exceeded, -2 for
+ * another mode or a bad ray. */
 int32_t or_alternatives(const or_ctx* c, const or_params* p, int64_t ray,
                         double eh_abs, double eh_rel, double et_abs, double et_rel,
                         double* alpha_out, int32_t max_out);

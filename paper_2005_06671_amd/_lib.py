@@ -124,10 +124,19 @@ def lib() -> C.CDLL:
     global _lib
     with _lock:
         if _lib is None:
+            how = ("build it with `python -c 'import __graft_entry__ as g; g.build()'` or "
+                   "`python paper_2005_06671_amd/build.py`")
             if not os.path.exists(LIB_PATH):
-                raise ImportError(
-                    f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
-                    " or `python paper_2005_06671_amd/build.py`")
+                raise ImportError(f"{LIB_PATH} is missing: {how}")
+            from . import build as _build
+            try:
+                with open(_build.HASH_FILE) as f:
+                    built = f.read().strip()
+            except OSError:
+                built = ""
+            if built != _build.source_hash():
+                raise ImportError(f"{LIB_PATH} was built from other sources than the ones next "
+                                  f"to it (stale): {how}")
             L = C.CDLL(LIB_PATH)
             for name, (res, args) in SIGNATURES.items():
                 f = getattr(L, name)

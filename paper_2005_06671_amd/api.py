@@ -465,47 +465,65 @@ def probe_gather(src: torch.Tensor, window: int = 0, iters: int = 64, n_threads:
 class ShadowCast(torch.autograd.Function):
     """s = shadow(h, elev, azim) with the hand-written adjoint kernel as backward.
 
-    The forward records each ray's deciding sample (4 bytes per ray), so the
-    backward applies the chain rule without replaying the descent.
+    By default the forward keeps only the heights, the max-mip and (exact mode)
+    the tap-bound pyramid, and the backward recomputes every ray's decisions
+    (ss_shadow_cast_backward) before applying the chain rule.  With record=True
+    the forward also writes each ray's deciding sample (4 bytes per ray,
+    ss_shadow_cast_save) and the backward reads it instead of replaying
+    (ss_shadow_cast_backward_saved); both give the same gradient up to the order
+    of the atomic sums.
     h: float32 CUDA [rows, width]; elev, azim: 0-d float64 tensors (CPU or CUDA).
     Gradients: dL/dh float32 (same device as h), dL/delev and dL/dazim float64.
     """
 
     @staticmethod
-    def forward(ctx, h, elev, azim, texel_m, ang_radius, params, window=None):
+    def forward(ctx, h, elev, azim, texel_m, ang_radius, params, window=None, record=False):
         e = float(elev)
         a = float(azim)
         hd = h.detach().contiguous()
         mm = maxmip(hd)
         bound = _bound_for(hd, params, None)
-        s, sample = shadow_cast_save(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound,
-                                     window=window)
-        ctx.save_for_backward(hd, mm, bound, sample)
-        ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim, window)
+        if record:
+            s, sample = shadow_cast_save(hd, texel_m, e, a, ang_radius, params, mm=mm,
+                                         bound=bound, window=window)
+        else:
+            s = shadow_cast(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound,
+                            window=window)
+            sample = hd.new_empty(0, dtype=torch.int32)
+        ctx.save_for_backward(hd, mm, bound if bound is not None else hd.new_empty(0), sample)
+        ctx.has_bound = bound is not None
+        ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim, window, record)
         return s
 
     @staticmethod
     def backward(ctx, grad_s):
         hd, mm, bound, sample = ctx.saved_tensors
-        texel_m, e, a, ang_radius, params, elev, azim, window = ctx.cfg
+        texel_m, e, a, ang_radius, params, elev, azim, window, record = ctx.cfg
+        bound = bound if ctx.has_bound else None
         g = grad_s.contiguous()
-        gh, gsun = shadow_cast_backward_saved(hd, texel_m, e, a, sample, g, ang_radius, params,
-                                              mm=mm, bound=bound, window=window)
+        if record:
+            gh, gsun = shadow_cast_backward_saved(hd, texel_m, e, a, sample, g, ang_radius,
+                                                  params, mm=mm, bound=bound, window=window)
+        else:
+            gh, gsun = shadow_cast_backward(hd, texel_m, e, a, g, ang_radius, params, mm=mm,
+                                            bound=bound, window=window)
         ge = gsun[0].to(elev.device) if isinstance(elev, torch.Tensor) else None
         ga = gsun[1].to(azim.device) if isinstance(azim, torch.Tensor) else None
-        return gh, ge, ga, None, None, None, None
+        return gh, ge, ga, None, None, None, None, None
 
 
 def shadow(h, elev, azim, texel_m, ang_radius=SUN_RADIUS_RAD, params: Params | None = None,
-           window=None):
+           window=None, record: bool = False):
     """Differentiable shadow factor (see ShadowCast); window = (x0, y0, w, h)
-    limits the ray origins, the gradient still covers every height."""
+    limits the ray origins, the gradient still covers every height.  The
+    backward recomputes the descent's decisions; record=True stores 4 bytes per
+    ray in the forward instead."""
     params = params or Params()
     if not isinstance(elev, torch.Tensor):
         elev = torch.tensor(float(elev), dtype=torch.float64)
     if not isinstance(azim, torch.Tensor):
         azim = torch.tensor(float(azim), dtype=torch.float64)
-    return ShadowCast.apply(h, elev, azim, texel_m, ang_radius, params, window)
+    return ShadowCast.apply(h, elev, azim, texel_m, ang_radius, params, window, bool(record))
 
 
 def shadow_points_backward(h: torch.Tensor, texel_m: float, elev: float, azim: float,
@@ -615,7 +633,7 @@ def batched_workspace_bytes(n_tiles: int, n_suns: int) -> int:
     return L.lib().ss_batched_workspace_bytes(n_tiles, n_suns)
 
 
-def _alloc_batch(heights, suns, outs, mms, windows=None):
+def _alloc_batch(heights, suns, outs, mms, windows=None, ws=None):
     dev = heights[0].device
     windows = windows or [None] * len(heights)
     if mms is None:
@@ -630,8 +648,11 @@ def _alloc_batch(heights, suns, outs, mms, windows=None):
             o = outs[t][k]
             _check_ray_buf(o, heights[t], windows[t], torch.float32, "out")
             ptrs[t * len(suns) + k] = o.data_ptr()
-    ws = torch.empty(max(256, batched_workspace_bytes(len(heights), len(suns))), dtype=torch.uint8,
-                     device=dev)
+    need = max(256, batched_workspace_bytes(len(heights), len(suns)))
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    elif ws.dtype != torch.uint8 or ws.numel() < need or not ws.is_cuda or ws.data_ptr() % 256:
+        raise ValueError(f"ws must be a 256-byte aligned uint8 CUDA tensor of >= {need} bytes")
     return mms, outs, ptrs, ws
 
 
@@ -644,18 +665,19 @@ def _bounds_for(heights, params, bounds):
 
 
 def shadow_cast_batched(heights, texels, suns, params: Params | None = None, outs=None, mms=None,
-                        windows=None, bounds=None):
+                        windows=None, bounds=None, ws=None):
     """s for every (tile, sun): returns outs[t][k] (float32, shape of tile t or
     of its ray window).
 
     Builds every tile's mipmap (and, in the exact mode, its tap-bound pyramid
     into ``bounds``) and runs one launch over every ray block of every (tile, sun)
     (flat by default; SS_BATCH_FORM=persistent selects the persistent form).
+    ``ws``: the workspace (uint8, batched_workspace_bytes), allocated if None.
     """
     params = params or Params()
     if len(heights) == 0 or len(suns) == 0:
         return [[] for _ in heights]
-    mms, outs, ptrs, ws = _alloc_batch(heights, suns, outs, mms, windows)
+    mms, outs, ptrs, ws = _alloc_batch(heights, suns, outs, mms, windows, ws)
     bounds = _bounds_for(heights, params, bounds)
     tiles, ss = _batch_structs(heights, mms, texels, suns, windows, bounds)
     p = params.c()

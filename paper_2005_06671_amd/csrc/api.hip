@@ -267,11 +267,13 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
   // concatenated runs: run j traces N'_j levels (top level N'_j - 1) and
   // covers 2^(N'_j - 1) texels of travel; enough runs to reach the cap, or
   // to span the tile diagonal without one
+  // run j starts at half-texel grid index a0_j, i.e. at ray length
+  // tau_j = (a0_j + 1) delta/2 (run_start_len)
   const double need = max_len_m > 0.0 ? max_len_m / t->texel_m
                                       : sqrt((double)W * W + (double)H * H) + 2.0;
-  double tau = 0.5 * delta, covered = 0.0;
-  int j = 0;
-  K->tau[0] = (float)tau;
+  const double half_delta = 0.5 * delta;
+  double covered = 0.0;
+  int j = 0, ga = 0;
   for (;;) {
     if (j >= SS_MAXSEG) return SS_ERR_UNSUPPORTED;
     int np = rp.schedule == SS_SCHED_EQUAL ? rp.n_prime0 : rp.n_prime0 + j;
@@ -279,14 +281,16 @@ static int32_t make_tilek(const ss_tile* t, const ss_sun* s, const Resolved& rp,
     if (np > L) np = L;
     if (np < 1) np = 1;
     K->m0[j] = np - 1;
-    K->a0[j] = j == 0 ? 0 : K->a0[j - 1] + (2 << K->m0[j - 1]);
-    tau += ldexp(delta, np - 1);
+    K->a0[j] = ga;
+    K->tau[j] = run_start_len(ga, half_delta);
+    ga += 2 << K->m0[j];
     covered += ldexp(1.0, np - 1);
-    K->tau[j + 1] = (float)tau;
     j++;
     if (rp.n_segments > 0 ? j >= rp.n_segments : covered >= need) break;
   }
   K->nseg = j;
+  K->tau[j] = run_start_len(ga, half_delta);
+  const double tau = (double)(ga + 1) * half_delta;
   // uniform steps stop at the cap, or without one at the tile edge and at the
   // latest after the runs' extent (the tile diagonal)
   K->ucap = max_len_m > 0.0 ? (float)(max_len_m / t->texel_m * delta) : (float)tau;
@@ -590,10 +594,12 @@ extern "C" int32_t ss_shadow_cast_backward_saved(const ss_tile* tile, const ss_s
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Workspace: SS_NXCD queue counters, then the tables (pair parameter blocks, output
-// pointers, item prefix sums, per-XCD band prefix sums, block-grid widths).
+// Workspace: SS_NXCD queue counters, the tables the batched kernels read (pair
+// parameter blocks, output pointers, block prefix sums, per-XCD queue prefix
+// sums, block-grid widths), then the staged compact image they are expanded
+// from (per-tile templates and records, per-pair records).
 struct WsLayout {
-  size_t counter, pairs, outs, start, xstart, nbx, total;
+  size_t counter, pairs, outs, start, xstart, nbx, tmpl, stile, spair, total;
 };
 
 static bool ws_layout(int32_t n_tiles, int32_t n_suns, WsLayout* L) {
@@ -605,7 +611,10 @@ static bool ws_layout(int32_t n_tiles, int32_t n_suns, WsLayout* L) {
   L->start = L->outs + align256(np * sizeof(float*));
   L->xstart = L->start + align256((np + 1) * sizeof(long long));
   L->nbx = L->xstart + align256((size_t)SS_NXCD * (np + 1) * sizeof(long long));
-  L->total = L->nbx + align256(np * sizeof(int));
+  L->tmpl = L->nbx + align256(np * sizeof(int));
+  L->stile = L->tmpl + align256((size_t)n_tiles * sizeof(TileK));
+  L->spair = L->stile + align256(((size_t)n_tiles + 1) * sizeof(StageTile));
+  L->total = L->spair + align256(np * sizeof(StagePair));
   return true;
 }
 
@@ -615,66 +624,87 @@ extern "C" int64_t ss_batched_workspace_bytes(int32_t n_tiles, int32_t n_suns) {
   return (int64_t)L.total;
 }
 
-// Host image of the workspace tables (everything after the counter).
-struct BatchTables {
-  std::vector<unsigned char> bytes;  // laid out as WsLayout from offset L.pairs
+// Host side of a batch: its description and the compact image to stage.
+struct BatchImage {
+  std::vector<TileK> tmpl;       // per tile: the set-up for its first sun
+  std::vector<StageTile> stile;  // per tile + totals
+  std::vector<StagePair> spair;  // per (tile, sun)
   BatchDesc bd;
   Resolved rp;
 };
 
-static int32_t build_tables(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
-                            int32_t n_suns, const ss_params* params, float* const* d_shadow,
-                            int ray_tile, BatchTables* bt) {
+// Forms the FP64 set-up of every (tile, sun) pair on the host; each pair's
+// parameter block equals make_tilek's for that pair (the expand kernel rebuilds
+// it from the tile's template, the pair's sun fields and its run starts).
+static int32_t build_image(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                           int32_t n_suns, const ss_params* params, float* const* d_shadow,
+                           int ray_tile, BatchImage* bi) {
   int32_t rc;
-  if ((rc = resolve_params(params, &bt->rp))) return rc;
-  if (ray_tile) bt->rp.ray_tile = ray_tile;
-  WsLayout L;
-  if (!ws_layout(n_tiles, n_suns, &L)) return SS_ERR_INVALID_ARG;
+  if ((rc = resolve_params(params, &bi->rp))) return rc;
+  if (ray_tile) bi->rp.ray_tile = ray_tile;
   const size_t np = (size_t)n_tiles * n_suns;
-  bt->bytes.assign(L.total - L.pairs, 0);
-  unsigned char* base = bt->bytes.data() - L.pairs;
-  TileK* pairs = reinterpret_cast<TileK*>(base + L.pairs);
-  float** outs = reinterpret_cast<float**>(base + L.outs);
-  long long* start = reinterpret_cast<long long*>(base + L.start);
-  long long* xstart = reinterpret_cast<long long*>(base + L.xstart);
-  int* nbxs = reinterpret_cast<int*>(base + L.nbx);
-  long long items = 0;
+  bi->tmpl.assign(n_tiles, TileK());
+  bi->stile.assign((size_t)n_tiles + 1, StageTile());
+  bi->spair.assign(np, StagePair());
+  long long items = 0, xq[SS_NXCD] = {0};
   for (int t = 0; t < n_tiles; ++t) {
+    StageTile& st = bi->stile[t];
+    st.start = items;
+    for (int x = 0; x < SS_NXCD; ++x) st.xt[x] = xq[x];
     for (int k = 0; k < n_suns; ++k) {
       const size_t p = (size_t)t * n_suns + k;
-      if ((rc = make_tilek(&tiles[t], &suns[k], bt->rp, params->max_len_m, params->body_radius_m,
-                           &pairs[p])))
+      TileK K;
+      if ((rc = make_tilek(&tiles[t], &suns[k], bi->rp, params->max_len_m, params->body_radius_m,
+                           &K)))
         return rc;
-      outs[p] = d_shadow[p];
-      int nbx, nb;
-      grid_for(pairs[p], bt->rp.ray_tile, &nbx, &nb);
-      nbxs[p] = nbx;
-      start[p] = items;
-      items += (nb + SS_ITEM_BLOCKS - 1) / SS_ITEM_BLOCKS;
+      if (k == 0) {
+        bi->tmpl[t] = K;
+        int nbx, nb;
+        grid_for(K, bi->rp.ray_tile, &nbx, &nb);
+        st.nbx = nbx;
+        st.items = (nb + SS_ITEM_BLOCKS - 1) / SS_ITEM_BLOCKS;
+      }
+      StagePair& sp = bi->spair[p];
+      memcpy(sp.sun, &K.Lx, sizeof(sp.sun));
+      sp.half_delta = 0.5 * (tiles[t].texel_m / cos(suns[k].elev_rad));
+      sp.out = d_shadow[p];
     }
+    items += (long long)n_suns * st.items;
+    // queue x holds band x of every pair: [x n / SS_NXCD, (x + 1) n / SS_NXCD) of its n items
+    for (int x = 0; x < SS_NXCD; ++x)
+      xq[x] += (long long)n_suns *
+               ((long long)(x + 1) * st.items / SS_NXCD - (long long)x * st.items / SS_NXCD);
   }
-  start[np] = items;
-  // XCD x's queue: band x of every pair, [x n / SS_NXCD, (x + 1) n / SS_NXCD) of its n items
-  for (int x = 0; x < SS_NXCD; ++x) {
-    long long* row = xstart + (size_t)x * (np + 1);
-    long long q = 0;
-    for (size_t p = 0; p < np; ++p) {
-      const long long n = start[p + 1] - start[p];
-      row[p] = q;
-      q += (long long)(x + 1) * n / SS_NXCD - (long long)x * n / SS_NXCD;
-    }
-    row[np] = q;
-  }
-  bt->bd.n_pairs = (int)np;
-  bt->bd.n_tiles = n_tiles;
-  bt->bd.n_suns = n_suns;
-  bt->bd.total_items = items;
+  StageTile& tot = bi->stile[n_tiles];
+  tot.start = items;
+  for (int x = 0; x < SS_NXCD; ++x) tot.xt[x] = xq[x];
+  bi->bd.n_pairs = (int)np;
+  bi->bd.n_tiles = n_tiles;
+  bi->bd.n_suns = n_suns;
+  bi->bd.total_items = items;
+  return SS_OK;
+}
+
+// Enqueues the staging of the image and its expansion into the tables.
+static int32_t stage_image(const BatchImage& bi, unsigned char* ws, hipStream_t s) {
+  WsLayout L;
+  ws_layout(bi.bd.n_tiles, bi.bd.n_suns, &L);
+  SS_HIP(launch_stage(ws + L.tmpl, bi.tmpl.data(), bi.tmpl.size() * sizeof(TileK), s));
+  SS_HIP(launch_stage(ws + L.stile, bi.stile.data(), bi.stile.size() * sizeof(StageTile), s));
+  SS_HIP(launch_stage(ws + L.spair, bi.spair.data(), bi.spair.size() * sizeof(StagePair), s));
+  SS_HIP(launch_expand(reinterpret_cast<const TileK*>(ws + L.tmpl),
+                       reinterpret_cast<const StageTile*>(ws + L.stile),
+                       reinterpret_cast<const StagePair*>(ws + L.spair), bi.bd.n_tiles,
+                       bi.bd.n_suns, reinterpret_cast<TileK*>(ws + L.pairs),
+                       reinterpret_cast<float**>(ws + L.outs),
+                       reinterpret_cast<long long*>(ws + L.start),
+                       reinterpret_cast<long long*>(ws + L.xstart),
+                       reinterpret_cast<int*>(ws + L.nbx), s));
   return SS_OK;
 }
 
 static int32_t check_batch(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns, int32_t n_suns,
-                           const ss_params* params, float* const* d_shadow, void* d_workspace,
-                           int64_t ws_bytes) {
+                           const ss_params* params, float* const* d_shadow) {
   if (n_tiles < 0 || n_suns < 0) return SS_ERR_INVALID_ARG;
   if (n_tiles == 0 || n_suns == 0) return SS_OK;
   if (!tiles || !suns || !params || !d_shadow) return SS_ERR_INVALID_ARG;
@@ -689,18 +719,17 @@ static int32_t check_batch(const ss_tile* tiles, int32_t n_tiles, const ss_sun* 
     if ((rc = check_sun(&suns[k]))) return rc;
   for (int64_t p = 0; p < (int64_t)n_tiles * n_suns; ++p)
     if (!d_shadow[p]) return SS_ERR_INVALID_ARG;
+  if (ss_batched_workspace_bytes(n_tiles, n_suns) < 0) return SS_ERR_INVALID_ARG;
+  return SS_OK;
+}
+
+static int32_t check_workspace(int32_t n_tiles, int32_t n_suns, const void* d_workspace,
+                               int64_t ws_bytes) {
   const int64_t need = ss_batched_workspace_bytes(n_tiles, n_suns);
-  if (need < 0) return SS_ERR_INVALID_ARG;
   if (!d_workspace || ws_bytes < need) return SS_ERR_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) return SS_ERR_WORKSPACE;
   return SS_OK;
 }
-
-// Pinned staging for the tables of eager batched calls.
-static std::mutex g_stage_mu;
-static void* g_stage = nullptr;
-static size_t g_stage_cap = 0;
-static hipEvent_t g_stage_ev = nullptr;
 
 // The batched call's form: flat (one workgroup per ray block of every pair;
 // the default) or, with SS_BATCH_FORM=persistent in the environment, the
@@ -711,26 +740,29 @@ static bool batch_persistent() {
   return e && strcmp(e, "persistent") == 0;
 }
 
-static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchTables& bt,
-                             unsigned char* ws, int fuse, int n_wg, hipStream_t stream) {
+// Maximum mipmaps (and, in the exact mode, tap-bound pyramids) of every tile,
+// then the batched launch over tables already in the workspace.
+static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchDesc& bd,
+                             const Resolved& rp, unsigned char* ws, int fuse, int n_wg,
+                             hipStream_t stream) {
   WsLayout L;
-  ws_layout(n_tiles, bt.bd.n_suns, &L);
+  ws_layout(n_tiles, bd.n_suns, &L);
   for (int t = 0; t < n_tiles; ++t) {
-    int32_t rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows,
-                              const_cast<float*>(tiles[t].maxmip), fuse, stream);
+    int32_t rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows, tiles[t].maxmip,
+                              fuse, stream);
     if (rc) return rc;
     // the exact mode also reads each tile's tap-bound pyramid (sun-independent)
-    if (bt.rp.mode == SS_MODE_EXACT &&
-        (rc = ss_bound_build(tiles[t].height, tiles[t].width, tiles[t].rows,
-                             const_cast<float*>(tiles[t].bound), stream)))
+    if (rp.mode == SS_MODE_EXACT &&
+        (rc = ss_bound_build(tiles[t].height, tiles[t].width, tiles[t].rows, tiles[t].bound,
+                             stream)))
       return rc;
   }
-  if (!batch_persistent() && bt.bd.total_items < (1LL << 31)) {
+  if (!batch_persistent() && bd.total_items < (1LL << 31)) {
     SS_HIP(launch_batched_flat(reinterpret_cast<const TileK*>(ws + L.pairs),
                                reinterpret_cast<float* const*>(ws + L.outs),
                                reinterpret_cast<const long long*>(ws + L.start),
-                               reinterpret_cast<const int*>(ws + L.nbx), bt.bd, device_wg_group(),
-                               bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile, stream));
+                               reinterpret_cast<const int*>(ws + L.nbx), bd, device_wg_group(),
+                               rp.sphere, rp.mode, rp.ray_tile, stream));
     return SS_OK;
   }
   SS_HIP(launch_fill_u32(reinterpret_cast<unsigned int*>(ws + L.counter), 0u, SS_NXCD, stream));
@@ -739,42 +771,35 @@ static int32_t enqueue_batch(const ss_tile* tiles, int32_t n_tiles, const BatchT
                         reinterpret_cast<const long long*>(ws + L.start),
                         reinterpret_cast<const long long*>(ws + L.xstart),
                         reinterpret_cast<const int*>(ws + L.nbx),
-                        reinterpret_cast<unsigned int*>(ws + L.counter), bt.bd, bt.rp.sphere,
-                        bt.rp.mode, bt.rp.ray_tile, n_wg, stream));
+                        reinterpret_cast<unsigned int*>(ws + L.counter), bd, rp.sphere, rp.mode,
+                        rp.ray_tile, n_wg, stream));
   return SS_OK;
+}
+
+// The whole batched call on a workspace: stage, expand, build, launch; only
+// kernel launches, so it runs unchanged under a caller's stream capture.
+static int32_t batched_on(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                          int32_t n_suns, const ss_params* params, float* const* d_shadow,
+                          unsigned char* ws, hipStream_t s) {
+  BatchImage bi;
+  int32_t rc = build_image(tiles, n_tiles, suns, n_suns, params, d_shadow, 0, &bi);
+  if (rc) return rc;
+  if ((rc = stage_image(bi, ws, s))) return rc;
+  const bool persistent = batch_persistent() || bi.bd.total_items >= (1LL << 31);
+  const int n_wg = persistent ? batched_workgroups(bi.rp.sphere, bi.rp.mode, bi.rp.ray_tile) : 0;
+  return enqueue_batch(tiles, n_tiles, bi.bd, bi.rp, ws, 6, n_wg, s);
 }
 
 extern "C" int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
                                           int32_t n_suns, const ss_params* params,
                                           float* const* d_shadow, void* d_workspace,
                                           int64_t workspace_bytes, void* stream) {
-  int32_t rc = check_batch(tiles, n_tiles, suns, n_suns, params, d_shadow, d_workspace,
-                           workspace_bytes);
+  int32_t rc = check_batch(tiles, n_tiles, suns, n_suns, params, d_shadow);
   if (rc) return rc;
   if (n_tiles == 0 || n_suns == 0) return SS_OK;
-  BatchTables bt;
-  if ((rc = build_tables(tiles, n_tiles, suns, n_suns, params, d_shadow, 0, &bt))) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  unsigned char* ws = static_cast<unsigned char*>(d_workspace);
-  WsLayout L;
-  ws_layout(n_tiles, n_suns, &L);
-  {
-    std::lock_guard<std::mutex> lk(g_stage_mu);
-    if (!g_stage_ev) SS_HIP(hipEventCreateWithFlags(&g_stage_ev, hipEventDisableTiming));
-    SS_HIP(hipEventSynchronize(g_stage_ev));  // the previous call's copy has left the buffer
-    if (g_stage_cap < bt.bytes.size()) {
-      if (g_stage) SS_HIP(hipHostFree(g_stage));
-      g_stage = nullptr;
-      g_stage_cap = 0;
-      SS_HIP(hipHostMalloc(&g_stage, bt.bytes.size(), hipHostMallocDefault));
-      g_stage_cap = bt.bytes.size();
-    }
-    memcpy(g_stage, bt.bytes.data(), bt.bytes.size());
-    SS_HIP(hipMemcpyAsync(ws + L.pairs, g_stage, bt.bytes.size(), hipMemcpyHostToDevice, s));
-    SS_HIP(hipEventRecord(g_stage_ev, s));
-  }
-  const int n_wg = batched_workgroups(bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile);
-  return enqueue_batch(tiles, n_tiles, bt, ws, 6, n_wg, s);
+  if ((rc = check_workspace(n_tiles, n_suns, d_workspace, workspace_bytes))) return rc;
+  return batched_on(tiles, n_tiles, suns, n_suns, params, d_shadow,
+                    static_cast<unsigned char*>(d_workspace), (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------------
@@ -885,7 +910,7 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
     for (int rep = 0; rep < 3; ++rep) {
       SS_HIP(hipEventRecord(a, s));
       int32_t rc = maxmip_build(tiles[big].height, tiles[big].width, tiles[big].rows,
-                                const_cast<float*>(tiles[big].maxmip), f, s);
+                                tiles[big].maxmip, f, s);
       if (rc) return rc;
       SS_HIP(hipEventRecord(b, s));
       double ms = 0.0;
@@ -906,21 +931,18 @@ static int32_t tune(const ss_tile* tiles, int n_tiles, const ss_sun* suns, int n
     sub[k] = suns[idx];
     sub_out[k] = d_shadow[(size_t)big * n_suns + idx];
   }
-  WsLayout L;
-  ws_layout(1, ns, &L);
   best = 1e30;
   *best_tile = SS_TILE_8x8;
   const int shapes[4] = {SS_TILE_8x8, SS_TILE_16x4, SS_TILE_4x16, SS_TILE_32x2};
   for (int sh : shapes) {
-    BatchTables bt;
-    int32_t rc = build_tables(&tiles[big], 1, sub.data(), ns, params, sub_out.data(), sh, &bt);
+    BatchImage bi;
+    int32_t rc = build_image(&tiles[big], 1, sub.data(), ns, params, sub_out.data(), sh, &bi);
     if (rc) return rc;
-    SS_HIP(hipStreamSynchronize(s));
-    SS_HIP(hipMemcpy(ws + L.pairs, bt.bytes.data(), bt.bytes.size(), hipMemcpyHostToDevice));
-    const int n_wg = batched_workgroups(bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile);
+    if ((rc = stage_image(bi, ws, s))) return rc;
+    const int n_wg = batched_workgroups(bi.rp.sphere, bi.rp.mode, bi.rp.ray_tile);
     for (int rep = 0; rep < 3; ++rep) {
       SS_HIP(hipEventRecord(a, s));
-      if ((rc = enqueue_batch(&tiles[big], 1, bt, ws, *best_fuse, n_wg, s))) return rc;
+      if ((rc = enqueue_batch(&tiles[big], 1, bi.bd, bi.rp, ws, *best_fuse, n_wg, s))) return rc;
       SS_HIP(hipEventRecord(b, s));
       double ms = 0.0;
       SS_HIP(time_ms(a, b, &ms));
@@ -946,21 +968,19 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
                                           ss_plan** plan_out) {
   if (!plan_out) return SS_ERR_INVALID_ARG;
   *plan_out = nullptr;
-  int32_t rc = check_batch(tiles, n_tiles, suns, n_suns, params, d_shadow, d_workspace,
-                           workspace_bytes);
+  int32_t rc = check_batch(tiles, n_tiles, suns, n_suns, params, d_shadow);
   if (rc) return rc;
   if (n_tiles == 0 || n_suns == 0) return SS_ERR_INVALID_ARG;
+  if ((rc = check_workspace(n_tiles, n_suns, d_workspace, workspace_bytes))) return rc;
   hipStream_t s = (hipStream_t)stream;
   Resolved rp;
   resolve_params(params, &rp);
   // tune (mipmaps and tap-bound pyramids first: the ray kernels read them)
   for (int t = 0; t < n_tiles; ++t) {
-    rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows,
-                      const_cast<float*>(tiles[t].maxmip), 6, s);
+    rc = maxmip_build(tiles[t].height, tiles[t].width, tiles[t].rows, tiles[t].maxmip, 6, s);
     if (rc) return rc;
     if (rp.mode == SS_MODE_EXACT &&
-        (rc = ss_bound_build(tiles[t].height, tiles[t].width, tiles[t].rows,
-                             const_cast<float*>(tiles[t].bound), s)))
+        (rc = ss_bound_build(tiles[t].height, tiles[t].width, tiles[t].rows, tiles[t].bound, s)))
       return rc;
   }
   int tile_code = params->ray_tile, fuse = 6;
@@ -989,14 +1009,13 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
     if (!tile_code) tile_code = bt_code;
     fuse = bf;
   }
-  BatchTables bt;
-  if ((rc = build_tables(tiles, n_tiles, suns, n_suns, params, d_shadow, tile_code, &bt))) return rc;
+  BatchImage bi;
+  if ((rc = build_image(tiles, n_tiles, suns, n_suns, params, d_shadow, tile_code, &bi))) return rc;
   unsigned char* ws = static_cast<unsigned char*>(d_workspace);
-  WsLayout L;
-  ws_layout(n_tiles, n_suns, &L);
+  // the tables are expanded once, outside the graph; the graph holds the builds and the launch
+  if ((rc = stage_image(bi, ws, s))) return rc;
   SS_HIP(hipStreamSynchronize(s));
-  SS_HIP(hipMemcpy(ws + L.pairs, bt.bytes.data(), bt.bytes.size(), hipMemcpyHostToDevice));
-  const int n_wg = batched_workgroups(bt.rp.sphere, bt.rp.mode, bt.rp.ray_tile);
+  const int n_wg = batched_workgroups(bi.rp.sphere, bi.rp.mode, bi.rp.ray_tile);
   ss_plan* plan = new ss_plan();
   plan->ray_tile = tile_code;
   plan->fuse = fuse;
@@ -1008,7 +1027,7 @@ extern "C" int32_t ss_batched_plan_create(const ss_tile* tiles, int32_t n_tiles,
   }
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = enqueue_batch(tiles, n_tiles, bt, ws, fuse, n_wg, cs);
+    rc = enqueue_batch(tiles, n_tiles, bi.bd, bi.rp, ws, fuse, n_wg, cs);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (rc == SS_OK && e2 != hipSuccess) rc = hip_fail(e2);

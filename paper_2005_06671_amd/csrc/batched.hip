@@ -12,6 +12,9 @@
 // parameter blocks live in the workspace; the item index is wave-uniform, so
 // they are read with scalar loads.  Each ray runs the same device code as the
 // per-tile kernel, so the outputs are bit-identical to it.
+#include <stddef.h>
+#include <string.h>
+
 #include "kernels.h"
 #include "ray.h"
 
@@ -223,6 +226,96 @@ __global__ void fill_u32_kernel(unsigned int* p, unsigned int v, int n) {
 
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, p, v, n);
+  return hipGetLastError();
+}
+
+// ---- staging of the batch tables through kernel arguments ----
+
+#define SS_STAGE_WORDS 500
+struct StageChunk {
+  unsigned n;
+  unsigned w[SS_STAGE_WORDS];
+};
+
+__global__ __launch_bounds__(256) void stage_kernel(unsigned* __restrict__ dst, StageChunk c) {
+  for (unsigned k = threadIdx.x; k < c.n; k += 256) dst[k] = c.w[k];
+}
+
+hipError_t launch_stage(void* d_dst, const void* h_src, size_t bytes, hipStream_t stream) {
+  const unsigned* src = static_cast<const unsigned*>(h_src);
+  unsigned* dst = static_cast<unsigned*>(d_dst);
+  const size_t words = bytes / 4;
+  StageChunk c;
+  for (size_t k = 0; k < words; k += SS_STAGE_WORDS) {
+    c.n = (unsigned)(words - k < SS_STAGE_WORDS ? words - k : SS_STAGE_WORDS);
+    memcpy(c.w, src + k, c.n * sizeof(unsigned));
+    hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(256), 0, stream, dst + k, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// One wavefront per pair: the TileK words come from the tile's template except
+// the sun fields (from the pair's record) and the run starts (formed from the
+// template's grid indices and the pair's delta/2, as the host set-up forms them).
+static_assert(offsetof(TileK, ucap) == offsetof(TileK, Lx) + 11 * sizeof(float),
+              "the sun fields of TileK are contiguous");
+static_assert(sizeof(TileK) % 4 == 0, "TileK is copied by words");
+
+__global__ __launch_bounds__(64) void expand_kernel(const TileK* __restrict__ tmpl,
+                                                    const StageTile* __restrict__ st,
+                                                    const StagePair* __restrict__ sp, int n_tiles,
+                                                    int n_suns, TileK* __restrict__ pairs,
+                                                    float** __restrict__ outs,
+                                                    long long* __restrict__ start,
+                                                    long long* __restrict__ xstart,
+                                                    int* __restrict__ nbx) {
+  constexpr int NW = (int)(sizeof(TileK) / 4);
+  constexpr int W_SUN = (int)(offsetof(TileK, Lx) / 4);
+  constexpr int W_TAU = (int)(offsetof(TileK, tau) / 4);
+  const int p = blockIdx.x;
+  const int t = p / n_suns, k = p % n_suns;
+  const int n_pairs = n_tiles * n_suns;
+  const TileK& T = tmpl[t];
+  const StagePair& P = sp[p];
+  const unsigned* src = reinterpret_cast<const unsigned*>(&T);
+  unsigned* dst = reinterpret_cast<unsigned*>(&pairs[p]);
+  const int nseg = T.nseg;
+  for (int w = threadIdx.x; w < NW; w += 64) {
+    unsigned v = src[w];
+    if (w >= W_SUN && w < W_SUN + 12) {
+      v = __float_as_uint(P.sun[w - W_SUN]);
+    } else if (w >= W_TAU && w <= W_TAU + nseg) {
+      const int j = w - W_TAU;
+      const int a = j < nseg ? T.a0[j] : T.a0[nseg - 1] + (2 << T.m0[nseg - 1]);
+      v = __float_as_uint(run_start_len(a, P.half_delta));
+    }
+    dst[w] = v;
+  }
+  const long long items = st[t].items;
+  if (threadIdx.x == 0) {
+    outs[p] = P.out;
+    start[p] = st[t].start + (long long)k * items;
+    nbx[p] = st[t].nbx;
+    if (p == n_pairs - 1) start[n_pairs] = st[n_tiles].start;
+  }
+  if (xstart && threadIdx.x < SS_NXCD) {
+    const int x = threadIdx.x;
+    const long long band = (long long)(x + 1) * items / SS_NXCD - (long long)x * items / SS_NXCD;
+    long long* row = xstart + (size_t)x * (n_pairs + 1);
+    row[p] = st[t].xt[x] + (long long)k * band;
+    if (p == n_pairs - 1) row[n_pairs] = st[n_tiles].xt[x];
+  }
+}
+
+hipError_t launch_expand(const TileK* tmpl, const StageTile* st, const StagePair* sp, int n_tiles,
+                         int n_suns, TileK* pairs, float** outs, long long* start,
+                         long long* xstart, int* nbx, hipStream_t stream) {
+  const long long np = (long long)n_tiles * n_suns;
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(expand_kernel, dim3((unsigned)np), dim3(64), 0, stream, tmpl, st, sp, n_tiles,
+                     n_suns, pairs, outs, start, xstart, nbx);
   return hipGetLastError();
 }
 

@@ -39,6 +39,14 @@ struct TileK {
                              // this many (one device-full, a multiple of 8)
 };
 
+// Ray length where the run starting at half-texel grid index a begins:
+// tau = (a + 1) delta/2, one FP64 product rounded once to FP32.  The per-tile
+// set-up on the host and the batched call's expand kernel on the device both
+// form it this way, so their parameter blocks agree bit for bit.
+__host__ __device__ inline float run_start_len(int a, double half_delta) {
+  return (float)((double)(a + 1) * half_delta);
+}
+
 // Ray tile shapes: lanes of one wavefront cover TW x TH texels (TW * TH = 64),
 // a 256-thread workgroup covers 2 x 2 wavefront tiles.
 enum { SS_TILE_8x8 = 1, SS_TILE_16x4 = 2, SS_TILE_4x16 = 3, SS_TILE_32x2 = 4 };

@@ -6,6 +6,9 @@
 
 namespace ss {
 
+#define SS_ITEM_BLOCKS 1  // ray blocks (256 rays each) per queue item of the batched kernel
+#define SS_NXCD 8         // XCDs; workgroup ids are dealt round-robin over them
+
 // Maximum mipmap: levels [m_src+1, m_src+F] from level m_src (F <= 6).
 hipError_t launch_maxmip(const float* src, int sw, int sh, float* dst_base, const int* dst_off,
                          const int* dst_w, const int* dst_h, int F, hipStream_t stream);
@@ -55,6 +58,32 @@ hipError_t launch_batched_flat(const TileK* d_pairs, float* const* d_out_ptrs,
                                const BatchDesc& bd, int grp, bool sphere, int mode, int ray_tile,
                                hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, unsigned int v, int n, hipStream_t stream);
+
+// Compact image of a batch, formed on the host (FP64 set-up) and staged into
+// the workspace through kernel arguments (no host buffer outlives the call, no
+// host wait, capturable); the expand kernel turns it into the per-pair
+// parameter blocks and tables the batched kernels read.
+struct StageTile {        // n_tiles + 1 entries; the last holds the totals
+  long long items;        // ray blocks of each (tile, sun) pair of this tile
+  long long start;        // block index of the tile's first pair
+  long long xt[SS_NXCD];  // queue x's index of the tile's first pair (persistent form)
+  int nbx, pad;           // ray-block grid width
+};
+struct StagePair {        // one per (tile, sun) pair, tile-major
+  float sun[12];          // the TileK fields Lx .. ucap of this pair
+  double half_delta;      // delta/2 in FP64; run starts are run_start_len(a0_j, half_delta)
+  float* out;             // its output buffer
+};
+static_assert(sizeof(StageTile) % 4 == 0 && sizeof(StagePair) % 8 == 0, "word-staged records");
+// Copies `bytes` (a multiple of 4) from host memory into device memory by
+// kernel arguments, in chunks of about 2 KB.
+hipError_t launch_stage(void* d_dst, const void* h_src, size_t bytes, hipStream_t stream);
+// pairs[p] = the tile's template with the pair's sun fields and run starts;
+// outs, block starts, grid widths and (xstart != nullptr) the per-queue prefix
+// sums of every pair, with their totals in entry n_pairs.
+hipError_t launch_expand(const TileK* tmpl, const StageTile* st, const StagePair* sp, int n_tiles,
+                         int n_suns, TileK* pairs, float** outs, long long* start,
+                         long long* xstart, int* nbx, hipStream_t stream);
 int batched_workgroups(bool sphere, int mode, int ray_tile);
 
 // View rays (pinhole camera) onto the terrain; the host fills every field.
@@ -96,8 +125,5 @@ hipError_t launch_resample(const ResampleK& K, hipStream_t stream);
 hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
                                float* out, long long n_threads, hipStream_t stream);
 hipError_t launch_valu_probe(int iters, long long n_workgroups, float* out, hipStream_t stream);
-
-#define SS_ITEM_BLOCKS 1  // ray blocks (256 rays each) per queue item of the batched kernel
-#define SS_NXCD 8         // XCDs; workgroup ids are dealt round-robin over them
 
 }  // namespace ss

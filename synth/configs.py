@@ -66,7 +66,10 @@ def sun_list(name: str, tile: int = 0):
             out.append((math.radians(e), a0 + math.radians(10.0 * k / 63.0), SUN_RADIUS_RAD))
         return out
     if name == "polar":
-        return [(math.radians(0.2), 2.0 * math.pi * u(1)[0], SUN_RADIUS_RAD)]
+        # two azimuths at the same low elevation (the second drawn after the first)
+        a0 = u(1)[0]
+        a1 = u(1)[0]
+        return [(math.radians(0.2), 2.0 * math.pi * a, SUN_RADIUS_RAD) for a in (a0, a1)]
     raise KeyError(name)
 
 

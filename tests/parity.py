@@ -2,8 +2,10 @@
 
 A texel passes when |s_gpu - s_oracle| <= TOL.  A texel that differs by more
 passes only if the oracle's near-tie enumeration (decisions whose FP64 margin
-is below single-precision resolution may go either way) yields a valid result
-within TOL of the GPU value; everything else is a failure.  The enumeration
+is below single-precision resolution may go either way: for the descent its
+crossings, lower bounds and samples, for uniform stepping whether a step at the
+tile edge or the cap counts) yields a valid result within TOL of the GPU value;
+everything else is a failure.  The enumeration
 runs in the oracle alone and never reads GPU output.
 """
 from __future__ import annotations
@@ -53,10 +55,10 @@ def compare(h: np.ndarray, p: oracle.Params, s_gpu: np.ndarray, rays=None, tol: 
     capped = 0
     for k in bad[:max_alt]:
         alts = None
-        if p.mode == 0:
+        if p.mode in (0, 1, 2):
             alts = oracle.alternatives(h, p, int(idx[k]), EH[0], EH[1], ET[0], ET[1])
         if alts is None:
-            capped += 1 if p.mode == 0 else 0
+            capped += 1 if p.mode in (0, 1, 2) else 0
             unexplained.append((int(idx[k]), float(g[k]), float(s_or[k])))
             continue
         sv = disc(alts, p.ang_radius)

@@ -225,24 +225,6 @@ def test_full_size_sampled_parity(ss, name, k):
             assert_parity(st)
 
 
-def test_polar_sampled_parity(ss):
-    from synth import config, dem_for, sun_list
-    c = config("polar")
-    W, Hh, D = c["tiles"][0]
-    print("polar", flush=True)
-    hd = dem_for("polar", device=dev())
-    mm = ss.maxmip(hd)
-    e, a, r = sun_list("polar")[0]
-    params = ss.Params(radius_m=R, max_len_m=c["max_len"])
-    s = ss.shadow_cast(hd, D, e, a, r, params, mm=mm)
-    torch.cuda.synchronize()
-    h = hd.cpu().numpy()
-    p = oracle.Params(W, Hh, D, R, e, a, r, max_len_m=c["max_len"])
-    rays = sampled(W * Hh, 8000, 5)
-    st = compare(h, p, s.cpu().numpy(), rays, label="polar dp")
-    assert_parity(st)
-
-
 # ---------------------------------------------------------------- edge cases
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 3)])

@@ -75,3 +75,31 @@ def test_saved_forward_and_backward(ss, shape, D, radius, e_deg, az, cap, mode, 
     a, b = gh1.double(), gh2.double()
     assert float((a - b).norm()) <= 1e-5 * max(float(a.norm()), 1e-30)
     assert torch.allclose(gs1, gs2, rtol=1e-6, atol=1e-9 * float(gs1.abs().max()) + 1e-12)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_autograd_replays_by_default(ss, mode):
+    """shadow() recomputes the decisions in its backward unless record=True; the two give
+    the same gradients up to the order of the atomic sums, and the default path equals a
+    direct call of the replaying adjoint."""
+    shape, D = (192, 224), 20.0
+    h = torch.from_numpy(rough(shape, 77, 80.0)).cuda()
+    params = ss.Params(radius_m=R, mode=mode)
+    g = torch.from_numpy(np.random.default_rng(9).standard_normal(shape).astype(np.float32)).cuda()
+    grads = []
+    for record in (False, True):
+        hh = h.clone().requires_grad_(True)
+        et = torch.tensor(math.radians(1.2), dtype=torch.float64, requires_grad=True)
+        at = torch.tensor(0.9, dtype=torch.float64, requires_grad=True)
+        s = ss.shadow(hh, et, at, D, RL, params, record=record)
+        (s * g).sum().backward()
+        torch.cuda.synchronize()
+        grads.append((hh.grad.double(), float(et.grad), float(at.grad)))
+    gh_direct, gs_direct = ss.shadow_cast_backward(h, D, math.radians(1.2), 0.9, g, RL, params)
+    torch.cuda.synchronize()
+    (a, ea, aa), (b, eb, ab) = grads
+    assert float(a.norm()) > 0
+    assert float((a - b).norm()) <= 1e-5 * float(a.norm())
+    assert float((a - gh_direct.double()).norm()) <= 1e-5 * float(a.norm())
+    assert abs(ea - eb) <= 1e-6 * abs(ea) + 1e-12 and abs(aa - ab) <= 1e-6 * abs(aa) + 1e-12
+    assert abs(ea - float(gs_direct[0])) <= 1e-6 * abs(ea) + 1e-12

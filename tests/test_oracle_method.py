@@ -186,3 +186,41 @@ def test_tie_enumeration_contains_plain_path(orc):
         assert alts is not None
         a = alpha.flat[lin]
         assert np.any(alts == a) or (np.isinf(a) and np.any(np.isinf(alts)))
+
+
+@pytest.mark.parametrize("mode,step", [(1, 1.0), (1, 0.5), (2, 1.0)])
+def test_uniform_tie_enumeration(orc, mode, step):
+    """Uniform stepping's near-tie set: at zero tolerance exactly the plain
+    loop's minimum; with tolerance it always holds that minimum, and for a ray
+    whose last step sits at the tile edge also the minimum without that step
+    (computed independently by capping the plain loop just before it)."""
+    rows, W = 40, 56
+    h = fbm_like((rows, W), 31, 200.0)
+    p = orc.Params(W, rows, 10.0, R, math.radians(1.0), 0.0, RL, mode=mode, uniform_step=step)
+    _, alpha = orc.shadow(h, p)
+    for lin in range(0, W * rows, 11):
+        a0 = orc.alternatives(h, p, lin, 0.0, 0.0, 0.0, 0.0)
+        assert a0 is not None and len(a0) == 1
+        assert a0[0] == alpha.flat[lin] or (np.isinf(a0[0]) and np.isinf(alpha.flat[lin]))
+        a1 = orc.alternatives(h, p, lin, 1e-2, 1e-7, 1e-3, 1e-6)
+        assert np.any(a1 == alpha.flat[lin]) or np.isinf(alpha.flat[lin])
+    # a ray on the plane, nearly along +x, whose last step lands 1e-7 texel inside the
+    # edge x = W, where a wall raises the terrain: the plain loop counts that step and it
+    # decides; the enumeration must also offer the minimum without it, which the plain
+    # loop gives when capped just before that step
+    hp = fbm_like((rows, W), 32, 150.0)
+    hp[:, -1] += 600.0
+    i, j = 30, 20
+    k_edge = W - i - 1  # step k sits at x = i + 1/2 + (k + 1/2) cos(a)
+    cos_a = (W - 1e-7 - (i + 0.5)) / (k_edge + 0.5)
+    pp = orc.Params(W, rows, 10.0, math.inf, math.radians(1.0), math.acos(cos_a), RL, mode=1,
+                    uniform_step=1.0)
+    lin = j * W + i
+    _, a_plain, tr = orc.shadow(hp, pp, np.array([lin]), trace=True)
+    assert tr["n"][0] == k_edge
+    delta = 10.0 / math.cos(math.radians(1.0))
+    _, a_short = orc.shadow(hp, pp.replace(uniform_tmax_m=k_edge * delta), np.array([lin]))
+    assert a_short[0] > a_plain[0]
+    alts = orc.alternatives(hp, pp, lin, 1e-2, 1e-7, 1e-3, 1e-6)
+    assert np.any(alts == a_plain[0]) and np.any(alts == a_short[0])
+    assert orc.alternatives(hp, pp, lin, 0.0, 0.0, 0.0, 0.0).tolist() == [a_plain[0]]
