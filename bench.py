@@ -34,13 +34,15 @@ METRIC = "Mrays/s DP+max-mip vs uniform stepping (fwd, fwd+bwd) at |Δ|≤1e-4 o
 WORKLOAD = ("tile: 4096x4096 fp32 DEM, 5 m/texel, fBm 2 km + 2000 craters, sphere R=1737.4 km, "
             "8 suns elev U[0.5,3] deg, r_L=0.267 deg, 30 km rays")
 
-# Algorithmic VALU work per unit, in issue slots of one lane (full-rate FP32 /
-# INT32 op = 1; v_rcp / v_sqrt = 4, they issue at quarter rate), counted from
-# the formulas each unit evaluates.
-OPS_LB = 51       # one max-mip lower bound: piece split, child index, t(u), tip rise, fetch, argmin
-OPS_SAMPLE = 64   # one bilinear clearance sample of the descent (t_n, u, taps, tip rise, argmin)
-OPS_RAY = 200     # per ray: origin frame, exit, per-run clearance angle, disc fraction
-OPS_USTEP = 76    # one uniform step: sample + clearance tangent + running min
+# Algorithmic VALU work per unit, in lane operations, fixed from the kernel
+# formulas before tuning: one max-mip lower-bound evaluation (top-level DDA step
+# or child piece: t(u), the tip's lowest height over the piece, crossings,
+# index, compare) 35; one bilinear clearance sample (four taps, tip height,
+# clearance, argmin) 45; one uniform step 40.  Achieved = units x ops / kernel
+# time; the peak is the non-packed FP32 lane rate of the chip.
+OPS_LB = 35
+OPS_SAMPLE = 45
+OPS_USTEP = 40
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz VALU lane-slots (FP32 not packed)
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
@@ -62,6 +64,7 @@ DP_SOURCES = ["paper_2005_06671_amd/csrc/ray.h", "paper_2005_06671_amd/csrc/batc
               "paper_2005_06671_amd/csrc/common.h"]
 TRAFFIC_FILE = "descent_tile_traffic.json"
 COUNTERS_FILE = "descent_tile_counters.txt"
+COUNTERS_JSON = "descent_tile_counters.json"
 
 
 def traffic_from_profile():
@@ -76,6 +79,20 @@ def traffic_from_profile():
     if d.get("kernel_src_sha") != src_hash(DP_SOURCES):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def counters_from_profile():
+    """VALU counters of the descent kernel (one batched launch over the 8 suns) from the
+    committed summary, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", COUNTERS_JSON)
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_src_sha") != src_hash(DP_SOURCES):
+        return None
+    return d.get("flat_descent")
 
 
 def cpu_baseline(h_np, params_or, seconds=15.0):
@@ -189,6 +206,19 @@ def summarize_counters(csv_path, out_dir):
                      f"{v.get('SQ_INSTS_VALU', 0) / waves:.0f} | "
                      f"{v.get('SQ_THREAD_CYCLES_VALU', 0) / max(1.0, v.get('SQ_ACTIVE_INST_VALU', 1)):.1f} | "
                      f"{v.get('SQ_INSTS_VALU_TRANS_F32', 0) / waves:.0f} | {hr}")
+    flat = [n for n in acc if "flat_kernel<true, 8, 0>" in n]
+    if flat:
+        v = {c: sum(x) / len(x) for c, x in acc[flat[0]].items()}
+        with open(os.path.join(out_dir, COUNTERS_JSON), "w") as f:
+            json.dump({"kernel_src_sha": src_hash(DP_SOURCES), "kernel": flat[0],
+                       "flat_descent": {
+                           "SQ_INSTS_VALU": v.get("SQ_INSTS_VALU", 0.0),
+                           "SQ_WAVES": v.get("SQ_WAVES", 0.0),
+                           "active_lanes": v.get("SQ_THREAD_CYCLES_VALU", 0.0)
+                           / max(1.0, v.get("SQ_ACTIVE_INST_VALU", 1.0)),
+                           "L2_hit_rate": (v["TCC_HIT_sum"] / (v["TCC_HIT_sum"] + v["TCC_MISS_sum"])
+                                           if "TCC_HIT_sum" in v and "TCC_MISS_sum" in v
+                                           else None)}}, f, indent=1)
     with open(os.path.join(out_dir, COUNTERS_FILE), "w") as f:
         f.write("# rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU "
                 "SQ_INSTS_VALU_TRANS_F32 TCC_HIT_sum TCC_MISS_sum --kernel-include-regex "
@@ -303,6 +333,22 @@ def leg_accuracy(ss, h, mm, D, suns, c):
     return {"reference": "uniform stepping at delta/2 (dense half-texel grid), all suns",
             "descent": desc, "point_descent": point, "uniform_1_texel": uni1,
             "mean_s_dense": float(u2.mean()), "uniform_step_sweep": sweep}, exact
+
+
+def equal_error_speedup(err, sweep, descent_ms):
+    """Per-sun time of uniform stepping at the step whose mean |s - s_dense| equals err,
+    interpolated log-linearly in (step, error) and (step, time) between the sweep's
+    points, divided by the descent's per-sun time (> 1: the descent is faster at equal
+    mean error).  None if the sweep does not bracket err."""
+    pts = sorted((p["step_texels"], p["mean_abs"], p["launch_ms"]) for p in sweep)
+    for (s0, e0, t0), (s1, e1, t1) in zip(pts, pts[1:]):
+        if e0 <= err <= e1 and e0 > 0 and e1 > e0:
+            f = (math.log(err) - math.log(e0)) / (math.log(e1) - math.log(e0))
+            t = math.exp(math.log(t0) + f * (math.log(t1) - math.log(t0)))
+            step = math.exp(math.log(s0) + f * (math.log(s1) - math.log(s0)))
+            return {"uniform_step_texels": step, "uniform_ms_per_sun": t,
+                    "descent_ms_per_sun": descent_ms, "speedup": t / descent_ms}
+    return None
 
 
 def leg_schedules(ss, h, mm, D, suns):
@@ -450,9 +496,11 @@ def leg_diff(ss, reps=5):
     tb = _timed(fwd_bwd, reps)
     tr = _timed(fwd_bwd_replay, reps)
     n = W * H
-    return {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
-            "fwd_bwd_replay_mrays_s": n / (min(tr) / 1e3) / 1e6,
-            "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "fwd_bwd_replay_ms": min(tr)}
+    return {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6,
+            "fwd_bwd_mrays_s": n / (min(tr) / 1e3) / 1e6,
+            "fwd_bwd_record_mrays_s": n / (min(tb) / 1e3) / 1e6,
+            "fwd_ms": min(tf), "fwd_bwd_ms": min(tr), "fwd_bwd_record_ms": min(tb),
+            "backward": "replaying adjoint (decisions recomputed); record: 4 B/ray from the forward"}
 
 
 def leg_frame(ss, reps=10):
@@ -621,26 +669,90 @@ def leg_polar(ss, reps=3):
     gh = torch.zeros_like(h)
     gs = torch.zeros(2, dtype=torch.float64, device=h.device)
 
-    sample = torch.empty(h.shape, dtype=torch.int32, device=h.device)
-
     def fwd_bwd():
         ss.maxmip(h, out=mm)
-        ss.shadow_cast_save(h, D, e, a, r, p, mm=mm, out=out, sample=sample)
-        ss.shadow_cast_backward_saved(h, D, e, a, sample, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+        ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out)
+        ss.shadow_cast_backward(h, D, e, a, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
 
     fwd_bwd()
-    tb = _timed(fwd_bwd, 1)
+    tb = _timed(fwd_bwd, 2)
     n = W * H
+    ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out)
     mean_s = float(out.mean())
+    # uniform stepping at one texel (the paper's baseline), same cap and exits
+    pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
+    ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=out)
+    tu = _timed(lambda: ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=out), 2)
     bound = ss.bound_build(h)
     px = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_EXACT)
     tx = _timed(lambda: ss.shadow_cast(h, D, e, a, r, px, mm=mm, out=out, bound=bound), 1)
     res = {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
            "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "mean_s": mean_s,
+           "backward": "replaying adjoint (decisions recomputed)",
+           "uniform_1_texel_mrays_s": n / (min(tu) / 1e3) / 1e6, "uniform_1_texel_ms": min(tu),
+           "speedup_vs_uniform": min(tu) / min(tf),
            "exact_mrays_s": n / (min(tx) / 1e3) / 1e6, "exact_ms": min(tx), "maxmip": mm_res}
     del bound
     del h, mm, out, g, gh
     return res
+
+
+def leg_small(ss, reps=50):
+    """The 256^2 small configuration (20 m/texel, rays to the tile edge, e = 1.5 deg): descent
+    and one-texel uniform stepping, forward, per launch (launch-bound: 65536 rays)."""
+    from synth import config, dem_for, sun_list, R_MOON
+    c = config("small")
+    W, H, D = c["tiles"][0]
+    e, a, r = sun_list("small")[0]
+    h = dem_for("small", device="cuda")
+    mm = ss.maxmip(h)
+    out = torch_empty_like(h)
+    res = {}
+    for name, p in (("descent", ss.Params(radius_m=R_MOON)),
+                    ("uniform_1_texel", ss.Params(radius_m=R_MOON, mode=ss.SS_MODE_UNIFORM))):
+        ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out)
+        t = float(sorted(_timed(lambda: ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out),
+                                reps))[reps // 2])
+        res[f"{name}_launch_ms"] = t
+        res[f"{name}_mrays_s"] = W * H / (t / 1e3) / 1e6
+    res["speedup_vs_uniform"] = res["uniform_1_texel_launch_ms"] / res["descent_launch_ms"]
+    return res
+
+
+def torch_empty_like(h):
+    import torch
+    return torch.empty_like(h)
+
+
+def cpu_oracle_configs(seconds_each=4.0):
+    """The FP64 oracle (descent and one-texel uniform stepping) on the small tile in full and
+    on 2^16 random rays of the differentiable and polar tiles, extrapolated linearly to
+    their full ray counts (the oracle's cost is per ray)."""
+    import numpy as np
+    import oracle
+    from synth import config, dem_for, sun_list, R_MOON
+    threads = max(1, len(os.sched_getaffinity(0)))
+    out = {"cores": threads}
+    for name in ("small", "diff", "polar"):
+        c = config(name)
+        W, H, D = c["tiles"][0]
+        e, a, r = sun_list(name)[0]
+        h = dem_for(name, device="cuda").cpu().numpy()
+        rays = None if name == "small" else np.sort(
+            np.random.default_rng(99).choice(W * H, size=1 << 16, replace=False)).astype(np.int64)
+        n = W * H if rays is None else rays.size
+        po = oracle.Params(W, H, D, R_MOON, e, a, r, max_len_m=c["max_len"])
+        oracle.shadow(h, po, np.arange(1, dtype=np.int64))  # the oracle's mipmap, untimed
+        row = {"rays_timed": n, "extrapolated": rays is not None}
+        for mname, mode in (("descent", 0), ("uniform_1_texel", 1)):
+            t0 = time.perf_counter()
+            oracle.shadow_threaded(h, po.replace(mode=mode), rays, threads=threads)
+            dt = time.perf_counter() - t0
+            row[f"{mname}_mrays_s"] = n / dt / 1e6
+            row[f"{mname}_full_tile_s"] = dt * (W * H) / n
+        out[name] = row
+        del h
+    return out
 
 
 def leg_exact(ss, reps=2):
@@ -663,7 +775,8 @@ def leg_exact(ss, reps=2):
     return {"launch_ms": ts, "mrays_s": W * H * len(ts) / (sum(ts) / 1e3) / 1e6}
 
 
-LEGS = {"frame": lambda ss: leg_frame(ss), "stitch": lambda ss: leg_stitch(ss),
+LEGS = {"small": lambda ss: leg_small(ss),
+        "frame": lambda ss: leg_frame(ss), "stitch": lambda ss: leg_stitch(ss),
         "diff": lambda ss: leg_diff(ss), "exact": lambda ss: leg_exact(ss)}
 
 
@@ -796,7 +909,7 @@ def main():
         units.append([int(x) for x in cnt.cpu().tolist()])
     n_lb = float(np.sum([u[0] for u in units]))
     n_smp = float(np.sum([u[1] for u in units]))
-    ops_per_step = OPS_LB * n_lb + OPS_SAMPLE * n_smp + OPS_RAY * rays_per_step
+    ops_per_step = OPS_LB * n_lb + OPS_SAMPLE * n_smp
     # the events bracket the whole graph, so the max-mip build (0.2% of it) counts as
     # kernel time and the figure errs low
     achieved = ops_per_step / (avg_step_ms / 1e3) / 1e12
@@ -807,14 +920,22 @@ def main():
                           "of the 8 suns)",
                 "avg_launch_ms": avg_step_ms, "timed_span": "graph replay incl. max-mip build",
                 "lb_evals_per_ray": n_lb / rays_per_step, "samples_per_ray": n_smp / rays_per_step,
-                "ops_model": {"lb": OPS_LB, "sample": OPS_SAMPLE, "ray": OPS_RAY},
+                "ops_per_unit": {"lower_bound": OPS_LB, "bilinear_sample": OPS_SAMPLE},
                 "plan_ray_tile_fuse_depth": list(plan_cfg)}
+    cnt = counters_from_profile()
+    if cnt:
+        # issued VALU wavefront instructions against one per SIMD per 4 cycles (the full-rate
+        # issue of a 64-lane wavefront on a 16-lane SIMD), from the committed counters
+        simd_slots = 256 * 4 * 2.4e9 * (avg_step_ms / 1e3) / 4.0
+        roofline["issue_frac"] = cnt["SQ_INSTS_VALU"] / simd_slots
+        roofline["valu_instr_per_unit"] = cnt["SQ_INSTS_VALU"] * 64.0 / (n_lb + n_smp)
+        roofline["active_lanes_per_valu_instr"] = cnt["active_lanes"]
     mm_bytes = float(maxmip_bytes(ss, W, H))
     maxmip = {"bound": "hbm", "avg_launch_ms": avg_mm_ms,
               "achieved_GBs": mm_bytes / (avg_mm_ms / 1e3) / 1e9, "peak_GBs": PEAK_HBM_GBS,
               "frac": mm_bytes / (avg_mm_ms / 1e3) / 1e9 / PEAK_HBM_GBS,
               "note": "64 MiB source is L2/MALL resident between steps (warm)"}
-    ps_ops = ops_per_step / len(suns)
+    ps_ops = ops_per_step / len(suns)  # the per-sun launches do the same units
     extras = {"step_ms_p10_p50_p90": _pct(step_ms),
               "per_sun_launches": {
                   "ms_per_step": ps_ms, "mrays_s": rays_per_step / (ps_ms / 1e3) / 1e6,
@@ -833,33 +954,45 @@ def main():
                                               W * H + ss.maxmip_floats(W, H), roofline)
         extras["valu_ceiling"] = leg_valu(ss, dev)
         roofline["peak_measured_fma_tops"] = extras["valu_ceiling"]["fma_lane_tops"]
-        # uniform stepping, one texel per step, same suns, cap and exits
-        # (both launch shapes: the batched call, as the step, and per-sun launches)
+        # uniform stepping, one texel per step, same suns, cap and exits, timed like the
+        # step: the batched call over the 8 suns (max-mip build + one launch) after a
+        # warm-up, 5 event-timed repetitions; and as per-sun launches
         pu = ss.Params(radius_m=R_MOON, max_len_m=c["max_len"], mode=ss.SS_MODE_UNIFORM)
-        for k, (e, a, r) in enumerate(suns[:1]):
-            ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=outs[k])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ss.shadow_cast_batched([h], [D], suns, pu, outs=[outs], mms=[mm])
-        torch.cuda.synchronize()
-        tu = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        ss.maxmip(h, out=mm)
-        for k, (e, a, r) in enumerate(suns):
-            ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=outs[k])
-        torch.cuda.synchronize()
-        tu_ps = time.perf_counter() - t0
-        uniform = rays_per_step / tu / 1e6
+        ws_u = torch.empty(ss.batched_workspace_bytes(1, len(suns)), dtype=torch.uint8,
+                           device=dev)
+
+        def uniform_batched():
+            ss.shadow_cast_batched([h], [D], suns, pu, outs=[outs], mms=[mm], ws=ws_u)
+
+        def uniform_per_sun():
+            ss.maxmip(h, out=mm)
+            for k, (e, a, r) in enumerate(suns):
+                ss.shadow_cast(h, D, e, a, r, pu, mm=mm, out=outs[k])
+
+        uniform_batched()
+        t_ub = _timed(uniform_batched, 5)
+        uniform_per_sun()
+        t_ups = _timed(uniform_per_sun, 3)
+        uniform = rays_per_step / (float(np.median(t_ub)) / 1e3) / 1e6
         extras["uniform_mrays_s"] = uniform
+        extras["uniform_ms_per_step_p10_p50_p90"] = _pct(t_ub)
         extras["speedup_vs_uniform"] = value / uniform
-        extras["per_sun_launches"]["uniform_mrays_s"] = rays_per_step / tu_ps / 1e6
-        extras["per_sun_launches"]["speedup_vs_uniform"] = (
-            extras["per_sun_launches"]["mrays_s"] / (rays_per_step / tu_ps / 1e6))
+        u_ps = rays_per_step / (float(np.median(t_ups)) / 1e3) / 1e6
+        extras["per_sun_launches"]["uniform_mrays_s"] = u_ps
+        extras["per_sun_launches"]["speedup_vs_uniform"] = extras["per_sun_launches"]["mrays_s"] / u_ps
         ucnt = []
         for k, (e, a, r) in enumerate(suns[:2]):
-            _, cnt = ss.shadow_cast_counted(h, D, e, a, r, pu, mm=mm)
-            ucnt.append(int(cnt[1].item()))
+            _, cnt_u = ss.shadow_cast_counted(h, D, e, a, r, pu, mm=mm)
+            ucnt.append(int(cnt_u[1].item()))
         extras["uniform_steps_per_ray"] = float(np.mean(ucnt)) / (W * H)
+        u_ops = OPS_USTEP * extras["uniform_steps_per_ray"] * rays_per_step
+        extras["uniform_roofline_frac"] = (u_ops / (float(np.median(t_ub)) / 1e3) / 1e12
+                                           / PEAK_VALU_TOPS)
+        # equal-error comparison: the uniform step whose image error against dense stepping
+        # equals the descent's (log-linear between the sweep's steps), and its per-sun time
+        acc = extras["accuracy_vs_dense"]
+        extras["speedup_vs_uniform_equal_error"] = equal_error_speedup(
+            acc["descent"]["mean_abs"], acc["uniform_step_sweep"], avg_dp_ms)
         # the same-accuracy comparison: the exact mode (descent as incumbent, then
         # branch and bound over the max-mip tap-bound pyramid) returns the dense
         # half-texel stepping result bit for bit; one-texel stepping is coarser
@@ -871,30 +1004,38 @@ def main():
             "exact_over_uniform_1_texel": ex["mrays_s"] / extras["per_sun_launches"]["uniform_mrays_s"],
             "exact_bit_identical_to_dense": ex["bit_identical_to_dense"],
             "uniform_1_texel_mean_abs_error": extras["accuracy_vs_dense"]["uniform_1_texel"]["mean_abs"]}
-        # forward + backward (hand-written adjoint) for every sun: the recorded
-        # forward with the adjoint reading the record, and the replaying adjoint
+        extras["equal_accuracy"]["same_accuracy_figure"] = (
+            "exact mode (branch and bound over the max-mip tap bounds, output identical to "
+            "dense half-texel stepping): exact_over_dense_uniform_identical_output")
+        # forward + backward (hand-written adjoint) for every sun: the forward, then the
+        # adjoint recomputing the decisions (the autograd default), and the recorded form
+        # (4-byte deciding sample per ray written by the forward, read by the adjoint)
         g = torch.randn(H, W, generator=torch.Generator(device="cpu").manual_seed(7)).to(dev)
         gh = torch.zeros_like(h)
         gsun = torch.zeros(2, dtype=torch.float64, device=dev)
         samples = [torch.empty(h.shape, dtype=torch.int32, device=dev) for _ in suns]
-        for replay in (False, True):
-            for rep in range(2):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                ss.maxmip(h, out=mm)
-                for k, (e, a, r) in enumerate(suns):
-                    if replay:
-                        ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
-                        ss.shadow_cast_backward(h, D, e, a, g, r, params, mm=mm, grad_h=gh,
-                                                grad_sun=gsun)
-                    else:
-                        ss.shadow_cast_save(h, D, e, a, r, params, mm=mm, out=outs[k],
-                                            sample=samples[k])
-                        ss.shadow_cast_backward_saved(h, D, e, a, samples[k], g, r, params, mm=mm,
-                                                      grad_h=gh, grad_sun=gsun)
-                torch.cuda.synchronize()
-                tfb = time.perf_counter() - t0
-            extras["fwd_bwd_replay_mrays_s" if replay else "fwd_bwd_mrays_s"] = rays_per_step / tfb / 1e6
+
+        def fb_replay():
+            ss.maxmip(h, out=mm)
+            for k, (e, a, r) in enumerate(suns):
+                ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
+                ss.shadow_cast_backward(h, D, e, a, g, r, params, mm=mm, grad_h=gh, grad_sun=gsun)
+
+        def fb_record():
+            ss.maxmip(h, out=mm)
+            for k, (e, a, r) in enumerate(suns):
+                ss.shadow_cast_save(h, D, e, a, r, params, mm=mm, out=outs[k], sample=samples[k])
+                ss.shadow_cast_backward_saved(h, D, e, a, samples[k], g, r, params, mm=mm,
+                                              grad_h=gh, grad_sun=gsun)
+
+        fb_replay()
+        fb_record()
+        t_fr = float(np.median(_timed(fb_replay, 3)))
+        t_fs = float(np.median(_timed(fb_record, 3)))
+        extras["fwd_bwd_mrays_s"] = rays_per_step / (t_fr / 1e3) / 1e6
+        extras["fwd_bwd_record_mrays_s"] = rays_per_step / (t_fs / 1e3) / 1e6
+        del samples
+        extras["small_256"] = leg_small(ss)
         extras["differentiable_2048"] = leg_diff(ss)
         extras["frame"] = leg_frame(ss)
         extras["stitch_across_seam"] = leg_stitch(ss)
@@ -911,6 +1052,7 @@ def main():
         if not args.no_extras:
             extras["cpu_uniform_oracle"] = cpu_uniform_baseline(h.cpu().numpy(),
                                                                 po.replace(mode=1))
+            extras["cpu_oracle_configs"] = cpu_oracle_configs()
 
     line = {"metric": METRIC, "value": value, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,

@@ -39,7 +39,8 @@ def source_hash() -> str:
         h.update(os.path.basename(p).encode())
         with open(p, "rb") as f:
             h.update(f.read())
-    h.update(" ".join(FLAGS).encode())
+    # the flags without the include path, which differs between checkouts
+    h.update(" ".join(f for f in FLAGS if not f.startswith("-I")).encode())
     return h.hexdigest()
 
 
