@@ -488,7 +488,7 @@ def leg_diff(ss, reps=5):
 
     def fwd_bwd_replay():
         fwd()
-        ss.shadow_cast_backward(h, D, e, a, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+        ss.shadow_cast_backward_penumbra(h, D, e, a, out, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
 
     fwd_bwd()
     fwd_bwd_replay()
@@ -500,7 +500,8 @@ def leg_diff(ss, reps=5):
             "fwd_bwd_mrays_s": n / (min(tr) / 1e3) / 1e6,
             "fwd_bwd_record_mrays_s": n / (min(tb) / 1e3) / 1e6,
             "fwd_ms": min(tf), "fwd_bwd_ms": min(tr), "fwd_bwd_record_ms": min(tb),
-            "backward": "replaying adjoint (decisions recomputed); record: 4 B/ray from the forward"}
+            "backward": "replaying adjoint (decisions recomputed for rays with s strictly inside "
+                        "(0, 1)); record: 4 B/ray from the forward"}
 
 
 def leg_frame(ss, reps=10):
@@ -672,7 +673,7 @@ def leg_polar(ss, reps=3):
     def fwd_bwd():
         ss.maxmip(h, out=mm)
         ss.shadow_cast(h, D, e, a, r, p, mm=mm, out=out)
-        ss.shadow_cast_backward(h, D, e, a, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
+        ss.shadow_cast_backward_penumbra(h, D, e, a, out, g, r, p, mm=mm, grad_h=gh, grad_sun=gs)
 
     fwd_bwd()
     tb = _timed(fwd_bwd, 2)
@@ -688,7 +689,7 @@ def leg_polar(ss, reps=3):
     tx = _timed(lambda: ss.shadow_cast(h, D, e, a, r, px, mm=mm, out=out, bound=bound), 1)
     res = {"fwd_mrays_s": n / (min(tf) / 1e3) / 1e6, "fwd_bwd_mrays_s": n / (min(tb) / 1e3) / 1e6,
            "fwd_ms": min(tf), "fwd_bwd_ms": min(tb), "mean_s": mean_s,
-           "backward": "replaying adjoint (decisions recomputed)",
+           "backward": "replaying adjoint (decisions recomputed for rays with s in (0, 1))",
            "uniform_1_texel_mrays_s": n / (min(tu) / 1e3) / 1e6, "uniform_1_texel_ms": min(tu),
            "speedup_vs_uniform": min(tu) / min(tf),
            "exact_mrays_s": n / (min(tx) / 1e3) / 1e6, "exact_ms": min(tx), "maxmip": mm_res}
@@ -1008,7 +1009,8 @@ def main():
             "exact mode (branch and bound over the max-mip tap bounds, output identical to "
             "dense half-texel stepping): exact_over_dense_uniform_identical_output")
         # forward + backward (hand-written adjoint) for every sun: the forward, then the
-        # adjoint recomputing the decisions (the autograd default), and the recorded form
+        # adjoint recomputing the decisions of the rays with s strictly inside (0, 1) (the
+        # autograd default; the others have no derivative), and the recorded form
         # (4-byte deciding sample per ray written by the forward, read by the adjoint)
         g = torch.randn(H, W, generator=torch.Generator(device="cpu").manual_seed(7)).to(dev)
         gh = torch.zeros_like(h)
@@ -1019,7 +1021,8 @@ def main():
             ss.maxmip(h, out=mm)
             for k, (e, a, r) in enumerate(suns):
                 ss.shadow_cast(h, D, e, a, r, params, mm=mm, out=outs[k])
-                ss.shadow_cast_backward(h, D, e, a, g, r, params, mm=mm, grad_h=gh, grad_sun=gsun)
+                ss.shadow_cast_backward_penumbra(h, D, e, a, outs[k], g, r, params, mm=mm,
+                                                 grad_h=gh, grad_sun=gsun)
 
         def fb_record():
             ss.maxmip(h, out=mm)

@@ -169,13 +169,26 @@ int32_t ss_shadow_cast_counted(const ss_tile* tile, const ss_sun* sun, const ss_
                                float* d_shadow, unsigned long long* d_eval_count, void* stream);
 
 /* Adjoint of ss_shadow_cast (every mode).  Recomputes every ray's
- * decisions, then ACCUMULATES (+=) dL/dh into d_grad_height [rows][width] and
+ * decisions (rays with a zero upstream gradient are skipped: they contribute
+ * nothing), then ACCUMULATES (+=) dL/dh into d_grad_height [rows][width] and
  * dL/d(elev, azim) into d_grad_sun[2] (FP64), given dL/ds in d_grad_shadow.
  * The max-mipmap enters only through discrete choices and has zero gradient.
  * Accumulation uses atomics, so the summation order is not fixed. */
 int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
                                 const float* d_grad_shadow, float* d_grad_height,
                                 double* d_grad_sun, void* stream);
+
+/* ss_shadow_cast_backward given the forward's output d_shadow (ss_shadow_cast
+ * with the same tile, sun and params): s is exactly 0 or 1 only where the
+ * clearance puts the whole sun disc below or above it (|d| >= 1), where s has
+ * no derivative, so those rays (and rays whose upstream gradient is 0) are not
+ * replayed.  The accumulated gradients equal ss_shadow_cast_backward's up to
+ * the order of the atomic sums; the cost follows the penumbra, not the tile.
+ * d_shadow is [ray_h][ray_w] like d_grad_shadow. */
+int32_t ss_shadow_cast_backward_penumbra(const ss_tile* tile, const ss_sun* sun,
+                                         const ss_params* params, const float* d_shadow,
+                                         const float* d_grad_shadow, float* d_grad_height,
+                                         double* d_grad_sun, void* stream);
 
 /* ---- tiles in other gnomonic frames (Sec. 3.3 virtual texture, Sec. 4) ---- */
 

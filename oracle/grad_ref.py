@@ -144,3 +144,21 @@ def reference_gradient(h_np: np.ndarray, p, trace, grad_s: np.ndarray, rays=None
     g = torch.as_tensor(np.asarray(grad_s, dtype=np.float64).reshape(-1))
     (s * g).sum().backward()
     return h.grad.numpy(), float(e.grad), float(a.grad), s.detach().numpy()
+
+
+def sun_term_scale(h_np: np.ndarray, p, trace, grad_s: np.ndarray, rays=None):
+    """(sum_r |g_r ds_r/delev|, sum_r |g_r ds_r/dazim|) along the oracle's branch.
+
+    dL/d(elev, azim) = sum_r g_r ds_r/d(elev, azim) can cancel heavily (random
+    upstream gradients, rays on both sides of a ridge); the rounding error of
+    any evaluation of such a sum scales with the sum of the absolute terms, not
+    with the result.  Per-ray derivatives by forward-mode differentiation."""
+    from torch.func import jvp
+    h = torch.tensor(np.asarray(h_np, dtype=np.float64), dtype=F64)
+    e0 = torch.tensor(float(p.elev), dtype=F64)
+    a0 = torch.tensor(float(p.azim), dtype=F64)
+    one = torch.tensor(1.0, dtype=F64)
+    _, dse = jvp(lambda e: shadow_on_branch(h, e, a0, p, trace, rays), (e0,), (one,))
+    _, dsa = jvp(lambda a: shadow_on_branch(h, e0, a, p, trace, rays), (a0,), (one,))
+    g = torch.as_tensor(np.asarray(grad_s, dtype=np.float64).reshape(-1))
+    return float((g * dse).abs().sum()), float((g * dsa).abs().sum())

@@ -74,6 +74,9 @@ SIGNATURES = {
     "ss_shadow_cast_backward": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun),
                                             C.POINTER(SSParams), C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_void_p]),
+    "ss_shadow_cast_backward_penumbra": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun),
+                                                     C.POINTER(SSParams), C.c_void_p, C.c_void_p,
+                                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "ss_shadow_cast_save": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun), C.POINTER(SSParams),
                                         C.c_void_p, C.c_void_p, C.c_void_p]),
     "ss_shadow_cast_backward_saved": (C.c_int32, [C.POINTER(SSTile), C.POINTER(SSSun),

@@ -218,6 +218,33 @@ def shadow_cast_backward(h, texel_m, elev, azim, grad_s, ang_radius=SUN_RADIUS_R
     return grad_h, grad_sun
 
 
+def shadow_cast_backward_penumbra(h, texel_m, elev, azim, s, grad_s, ang_radius=SUN_RADIUS_RAD,
+                                  params=None, mm=None, grad_h=None, grad_sun=None, bound=None,
+                                  window=None):
+    """shadow_cast_backward given the forward's output s: rays at s = 0 or 1 (no derivative)
+    are not replayed; same accumulation."""
+    _dev_f32_2d(h)
+    _check_ray_buf(grad_s, h, window, torch.float32, "grad_s")
+    _check_ray_buf(s, h, window, torch.float32, "s")
+    params = params or Params()
+    if mm is None:
+        mm = maxmip(h)
+    bound = _bound_for(h, params, bound)
+    if grad_h is None:
+        grad_h = torch.zeros_like(h)
+    if grad_sun is None:
+        grad_sun = torch.zeros(2, dtype=torch.float64, device=h.device)
+    t = _tile(h, mm, texel_m, bound, window)
+    sn = _sun(elev, azim, ang_radius)
+    p = params.c()
+    L.check("ss_shadow_cast_backward_penumbra",
+            L.lib().ss_shadow_cast_backward_penumbra(C.byref(t), C.byref(sn), C.byref(p),
+                                                     s.data_ptr(), grad_s.data_ptr(),
+                                                     grad_h.data_ptr(), grad_sun.data_ptr(),
+                                                     _stream(h.device)))
+    return grad_h, grad_sun
+
+
 def shadow_cast_save(h, texel_m, elev, azim, ang_radius=SUN_RADIUS_RAD, params=None, mm=None,
                      out=None, bound=None, sample=None, window=None):
     """(s, sample): s as shadow_cast, and each ray's deciding sample index (int32, -1 none)."""
@@ -465,9 +492,11 @@ def probe_gather(src: torch.Tensor, window: int = 0, iters: int = 64, n_threads:
 class ShadowCast(torch.autograd.Function):
     """s = shadow(h, elev, azim) with the hand-written adjoint kernel as backward.
 
-    By default the forward keeps only the heights, the max-mip and (exact mode)
-    the tap-bound pyramid, and the backward recomputes every ray's decisions
-    (ss_shadow_cast_backward) before applying the chain rule.  With record=True
+    By default the forward keeps only the heights, the max-mip, (exact mode)
+    the tap-bound pyramid and its own output, and the backward recomputes the
+    decisions of every ray whose s lies strictly inside (0, 1) (the others have
+    no derivative; ss_shadow_cast_backward_penumbra) before applying the chain
+    rule.  With record=True
     the forward also writes each ray's deciding sample (4 bytes per ray,
     ss_shadow_cast_save) and the backward reads it instead of replaying
     (ss_shadow_cast_backward_saved); both give the same gradient up to the order
@@ -489,7 +518,7 @@ class ShadowCast(torch.autograd.Function):
         else:
             s = shadow_cast(hd, texel_m, e, a, ang_radius, params, mm=mm, bound=bound,
                             window=window)
-            sample = hd.new_empty(0, dtype=torch.int32)
+            sample = s  # the forward's values tell the backward which rays to replay
         ctx.save_for_backward(hd, mm, bound if bound is not None else hd.new_empty(0), sample)
         ctx.has_bound = bound is not None
         ctx.cfg = (texel_m, e, a, ang_radius, params, elev, azim, window, record)
@@ -505,8 +534,8 @@ class ShadowCast(torch.autograd.Function):
             gh, gsun = shadow_cast_backward_saved(hd, texel_m, e, a, sample, g, ang_radius,
                                                   params, mm=mm, bound=bound, window=window)
         else:
-            gh, gsun = shadow_cast_backward(hd, texel_m, e, a, g, ang_radius, params, mm=mm,
-                                            bound=bound, window=window)
+            gh, gsun = shadow_cast_backward_penumbra(hd, texel_m, e, a, sample, g, ang_radius,
+                                                     params, mm=mm, bound=bound, window=window)
         ge = gsun[0].to(elev.device) if isinstance(elev, torch.Tensor) else None
         ga = gsun[1].to(azim.device) if isinstance(azim, torch.Tensor) else None
         return gh, ge, ga, None, None, None, None, None

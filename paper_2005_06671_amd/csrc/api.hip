@@ -345,8 +345,9 @@ extern "C" int32_t ss_shadow_cast_save(const ss_tile* tile, const ss_sun* sun,
 }
 
 static int32_t backward_common(const ss_tile* tile, const ss_sun* sun, const ss_params* params,
-                               const int32_t* d_sample, const float* d_grad_shadow,
-                               float* d_grad_height, double* d_grad_sun, void* stream) {
+                               const int32_t* d_sample, const float* d_shadow,
+                               const float* d_grad_shadow, float* d_grad_height,
+                               double* d_grad_sun, void* stream) {
   Resolved rp;
   int32_t rc = resolve_params(params, &rp);
   if (rc) return rc;
@@ -358,7 +359,7 @@ static int32_t backward_common(const ss_tile* tile, const ss_sun* sun, const ss_
   TileK K;
   if ((rc = make_tilek(tile, sun, rp, params->max_len_m, params->body_radius_m, &K))) return rc;
   SS_HIP(launch_adjoint(K, rp.sphere, rp.mode, sun->elev_rad, sun->azim_rad, d_grad_shadow,
-                        d_sample, d_grad_height, d_grad_sun, (hipStream_t)stream));
+                        d_sample, d_shadow, d_grad_height, d_grad_sun, (hipStream_t)stream));
   return SS_OK;
 }
 
@@ -575,8 +576,18 @@ extern "C" int32_t ss_probe_valu(int32_t iters, int64_t n_workgroups, float* d_o
 extern "C" int32_t ss_shadow_cast_backward(const ss_tile* tile, const ss_sun* sun,
                                            const ss_params* params, const float* d_grad_shadow,
                                            float* d_grad_height, double* d_grad_sun, void* stream) {
-  return backward_common(tile, sun, params, nullptr, d_grad_shadow, d_grad_height, d_grad_sun,
-                         stream);
+  return backward_common(tile, sun, params, nullptr, nullptr, d_grad_shadow, d_grad_height,
+                         d_grad_sun, stream);
+}
+
+extern "C" int32_t ss_shadow_cast_backward_penumbra(const ss_tile* tile, const ss_sun* sun,
+                                                    const ss_params* params, const float* d_shadow,
+                                                    const float* d_grad_shadow,
+                                                    float* d_grad_height, double* d_grad_sun,
+                                                    void* stream) {
+  if (!d_shadow && tile && tile->width > 0 && tile->rows > 0) return SS_ERR_INVALID_ARG;
+  return backward_common(tile, sun, params, nullptr, d_shadow, d_grad_shadow, d_grad_height,
+                         d_grad_sun, stream);
 }
 
 extern "C" int32_t ss_shadow_cast_backward_saved(const ss_tile* tile, const ss_sun* sun,
@@ -584,8 +595,8 @@ extern "C" int32_t ss_shadow_cast_backward_saved(const ss_tile* tile, const ss_s
                                                  const float* d_grad_shadow, float* d_grad_height,
                                                  double* d_grad_sun, void* stream) {
   if (!d_sample && tile && tile->width > 0 && tile->rows > 0) return SS_ERR_INVALID_ARG;
-  return backward_common(tile, sun, params, d_sample, d_grad_shadow, d_grad_height, d_grad_sun,
-                         stream);
+  return backward_common(tile, sun, params, d_sample, nullptr, d_grad_shadow, d_grad_height,
+                         d_grad_sun, stream);
 }
 
 // ------------------------------------------------------------------------

@@ -34,9 +34,10 @@ hipError_t launch_points_adjoint(const TileK& T, bool sphere, int mode, double e
                                  float* gh, double* gsun, hipStream_t stream);
 
 // sample != nullptr: take the deciding samples from there instead of replaying.
+// sfwd != nullptr: the forward's shadow factors; rays at 0 or 1 are skipped.
 hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
-                          const float* gs, const int* sample, float* gh, double* gsun,
-                          hipStream_t stream);
+                          const float* gs, const int* sample, const float* sfwd, float* gh,
+                          double* gsun, hipStream_t stream);
 
 // Persistent batched launch over (tile, sun, ray block) items.
 struct BatchDesc {

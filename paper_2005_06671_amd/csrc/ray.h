@@ -242,12 +242,18 @@ __device__ __forceinline__ float terrain_above(const TileK& T, float qx, float q
 }
 
 // Visible part of the sun disc above a chord at d disc radii below its centre
-// (Sec. 3.4, Eq. 6 first term; circular segment).
+// (Sec. 3.4, Eq. 6 first term; circular segment).  s is exactly 0 or 1 when
+// |d| >= 1 (the disc wholly below or above the clearance, zero derivative) and
+// strictly inside (0, 1) otherwise, so the adjoint can tell the rays it may
+// skip from the forward's output alone.
 __device__ __forceinline__ float disc_fraction(float alpha, const TileK& T) {
   if (!(alpha < SS_INF)) return 1.0f;
-  const float d = fminf(fmaxf(alpha * T.inv_rL, -1.0f), 1.0f);
-  return (3.14159265358979f - acosf(d) + d * sqrtf(fmaxf(0.0f, 1.0f - d * d))) *
-         0.318309886183791f;
+  const float dd = alpha * T.inv_rL;
+  if (dd <= -1.0f) return 0.0f;
+  if (dd >= 1.0f) return 1.0f;
+  const float v = (3.14159265358979f - acosf(dd) + dd * sqrtf(fmaxf(0.0f, 1.0f - dd * dd))) *
+                  0.318309886183791f;
+  return fminf(fmaxf(v, 1.17549435e-38f), 0.99999994f);
 }
 
 // Clearance of a sample: the signed angle at p between L and the terrain point

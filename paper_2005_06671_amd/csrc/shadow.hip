@@ -202,15 +202,24 @@ __device__ __forceinline__ float adjoint_sample(const TileK& T, const SunTrig& s
   return a_hp;
 }
 
+// sfwd (may be null): the forward's shadow factors; a ray whose value is 0 or
+// 1 has |d| >= 1 (disc_fraction) and no derivative, so it is not replayed, nor
+// is one whose upstream gradient is 0: neither contributes anything.
 template <bool SPHERE, int MODE, bool SAVED>
 __device__ __forceinline__ void adjoint_ray(const TileK& T, const SunTrig& st, int li, int lj,
                                             const float* __restrict__ gs,
                                             const int* __restrict__ sample,
+                                            const float* __restrict__ sfwd,
                                             float* __restrict__ gh, double& ge, double& ga,
                                             const int* tab) {
   if (li < T.RW && lj < T.RH) {
     const int i = T.rx0 + li, j = T.ry0 + lj;
     const float g = gs[lj * T.RW + li];
+    if (g == 0.0f) return;
+    if (sfwd) {
+      const float sv = sfwd[lj * T.RW + li];
+      if (sv == 0.0f || sv == 1.0f) return;
+    }
     const float hp = T.h[j * T.W + i];
     Ray<SPHERE> r;
     ray_init(T, i, j, hp, r);
@@ -258,6 +267,7 @@ template <bool SPHERE, int TW, int MODE, bool SAVED>
 __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
                                                       const float* __restrict__ gs,
                                                       const int* __restrict__ sample,
+                                                      const float* __restrict__ sfwd,
                                                       float* __restrict__ gh,
                                                       double* __restrict__ gsun, int nbx,
                                                       int nblocks) {
@@ -274,7 +284,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
     if (vb >= nblocks) break;
     int i, j;
     coords_of<TW>(vb, nbx, i, j);
-    adjoint_ray<SPHERE, MODE, SAVED>(T, st, i, j, gs, sample, gh, ge, ga, tab);
+    adjoint_ray<SPHERE, MODE, SAVED>(T, st, i, j, gs, sample, sfwd, gh, ge, ga, tab);
   }
   ge = wave_sum_f64(ge);
   ga = wave_sum_f64(ga);
@@ -585,33 +595,34 @@ hipError_t launch_forward(const TileK& T, bool sphere, int mode, int ray_tile, b
 
 template <bool SPHERE, int MODE>
 static void adjoint_launch(const TileK& T, const SunTrig& st, const float* gs, const int* sample,
-                           float* gh, double* gsun, int nbx, int nb, hipStream_t stream) {
+                           const float* sfwd, float* gh, double* gsun, int nbx, int nb,
+                           hipStream_t stream) {
   if (sample)
     hipLaunchKernelGGL((adjoint_kernel<SPHERE, 8, MODE, true>),
                        dim3((nb + AdjBlocks<true>::n - 1) / AdjBlocks<true>::n), dim3(256), 0,
-                       stream, T, st, gs, sample, gh, gsun, nbx, nb);
+                       stream, T, st, gs, sample, sfwd, gh, gsun, nbx, nb);
   else
     hipLaunchKernelGGL((adjoint_kernel<SPHERE, 8, MODE, false>), dim3(nb), dim3(256), 0, stream, T,
-                       st, gs, sample, gh, gsun, nbx, nb);
+                       st, gs, sample, sfwd, gh, gsun, nbx, nb);
 }
 
 template <bool SPHERE>
 static void adjoint_mode(const TileK& T, int mode, const SunTrig& st, const float* gs,
-                         const int* sample, float* gh, double* gsun, int nbx, int nb,
-                         hipStream_t stream) {
+                         const int* sample, const float* sfwd, float* gh, double* gsun, int nbx,
+                         int nb, hipStream_t stream) {
   if (mode == SS_MODE_EXACT)
-    adjoint_launch<SPHERE, SS_MODE_EXACT>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_EXACT>(T, st, gs, sample, sfwd, gh, gsun, nbx, nb, stream);
   else if (mode == SS_MODE_POINT)
-    adjoint_launch<SPHERE, SS_MODE_POINT>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_POINT>(T, st, gs, sample, sfwd, gh, gsun, nbx, nb, stream);
   else if (mode == SS_MODE_UNIFORM)
-    adjoint_launch<SPHERE, SS_MODE_UNIFORM>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_UNIFORM>(T, st, gs, sample, sfwd, gh, gsun, nbx, nb, stream);
   else
-    adjoint_launch<SPHERE, SS_MODE_DP>(T, st, gs, sample, gh, gsun, nbx, nb, stream);
+    adjoint_launch<SPHERE, SS_MODE_DP>(T, st, gs, sample, sfwd, gh, gsun, nbx, nb, stream);
 }
 
 hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, double azim,
-                          const float* gs, const int* sample, float* gh, double* gsun,
-                          hipStream_t stream) {
+                          const float* gs, const int* sample, const float* sfwd, float* gh,
+                          double* gsun, hipStream_t stream) {
   SunTrig st;
   st.se = (float)sin(elev);
   st.ce = (float)cos(elev);
@@ -622,9 +633,9 @@ hipError_t launch_adjoint(const TileK& T, bool sphere, int mode, double elev, do
   grid_for(T, SS_TILE_8x8, &nbx, &nb);
   if (nb == 0) return hipSuccess;
   if (sphere)
-    adjoint_mode<true>(T, mode, st, gs, sample, gh, gsun, nbx, nb, stream);
+    adjoint_mode<true>(T, mode, st, gs, sample, sfwd, gh, gsun, nbx, nb, stream);
   else
-    adjoint_mode<false>(T, mode, st, gs, sample, gh, gsun, nbx, nb, stream);
+    adjoint_mode<false>(T, mode, st, gs, sample, sfwd, gh, gsun, nbx, nb, stream);
   return hipGetLastError();
 }
 

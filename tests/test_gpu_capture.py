@@ -40,6 +40,11 @@ def bits(t):
     return t.view(torch.int32)
 
 
+def levels(ss, mm):
+    """The mipmap's levels (the padding between them is never written)."""
+    return torch.cat([v.reshape(-1) for v in ss.maxmip_unpack(mm, 264, 200)])
+
+
 def close(a, b, rel):
     a, b = a.double(), b.double()
     return float((a - b).norm()) <= rel * max(float(a.norm()), 1e-300)
@@ -83,7 +88,7 @@ def test_graph_capture_matches_eager(ss, form, monkeypatch):
 
     def check(ref):
         mm_r, out_r, gh_r, gs_r, ob_r = ref
-        assert torch.equal(mm, mm_r)
+        assert torch.equal(levels(ss, mm), levels(ss, mm_r))
         assert torch.equal(bits(out), bits(out_r))
         assert close(gh, gh_r, 1e-5) and close(gs, gs_r, 1e-9)
         for row, row_r in zip(outs_b, ob_r):
@@ -124,7 +129,7 @@ def test_graph_capture_matches_eager(ss, form, monkeypatch):
     got = (mm.clone(), out.clone(), gh.clone(), gs.clone(), [[o.clone() for o in row] for row in outs_b])
     ref2 = eager_reference()
     assert not torch.equal(bits(ref2[1]), bits(ref[1]))
-    assert torch.equal(got[0], ref2[0])
+    assert torch.equal(levels(ss, got[0]), levels(ss, ref2[0]))
     assert torch.equal(bits(got[1]), bits(ref2[1]))
     assert close(got[2], ref2[2], 1e-5) and close(got[3], ref2[3], 1e-9)
     for row, row_r in zip(got[4], ref2[4]):

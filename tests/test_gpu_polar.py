@@ -10,8 +10,9 @@ sample keeps mostly those whose oracle s lies strictly inside (0, 1).
 * forward, uniform stepping at one texel (the paper's baseline), same bar;
 * the replaying adjoint (decisions recomputed in the backward) against the
   float64 reference gradient along the oracle's branch, on the well-conditioned
-  penumbra rays of a 2 M-ray random sample: relative L2 error of dL/dh and
-  relative error of dL/d(elev, azim) <= 1e-3."""
+  penumbra rays of a 2 M-ray random sample: relative L2 error of dL/dh
+  <= 1e-3, and dL/d(elev, azim) within 1e-3 of the reference plus 1e-5 of the
+  absolute sum of their per-ray terms (the sums cancel heavily)."""
 import math
 
 import numpy as np
@@ -128,5 +129,11 @@ def test_polar_adjoint_replay(ss, polar):
     rel = np.linalg.norm(gh - ref_h) / np.linalg.norm(ref_h)
     print("rel err dL/dh", rel, "sun", gsun, ref_e, ref_a, flush=True)
     assert rel <= 1e-3
-    assert abs(gsun[0] - ref_e) <= 1e-3 * abs(ref_e)
-    assert abs(gsun[1] - ref_a) <= 1e-3 * max(abs(ref_a), 1e-3 * abs(ref_e))
+    # the sun terms are sums of ~2000 signed per-ray terms that cancel (the azimuth one to
+    # ~1/3500 of its absolute sum here): besides 1e-3 of the result, allow 1e-5 of the
+    # absolute sum, the rounding an FP32 evaluation of every term carries (the measured
+    # error is ~2e-6 of it)
+    abs_e, abs_a = grad_ref.sun_term_scale(P["h"], p, tr, g_r, rays=rays)
+    print("absolute sums of the sun terms", abs_e, abs_a, flush=True)
+    assert abs(gsun[0] - ref_e) <= 1e-3 * abs(ref_e) + 1e-5 * abs_e
+    assert abs(gsun[1] - ref_a) <= 1e-3 * abs(ref_a) + 1e-5 * abs_a

@@ -103,3 +103,26 @@ def test_autograd_replays_by_default(ss, mode):
     assert float((a - gh_direct.double()).norm()) <= 1e-5 * float(a.norm())
     assert abs(ea - eb) <= 1e-6 * abs(ea) + 1e-12 and abs(aa - ab) <= 1e-6 * abs(aa) + 1e-12
     assert abs(ea - float(gs_direct[0])) <= 1e-6 * abs(ea) + 1e-12
+
+
+@pytest.mark.parametrize("mode,step", MODES)
+def test_penumbra_backward_equals_full_replay(ss, mode, step):
+    """ss_shadow_cast_backward_penumbra (rays at s = 0 or 1 not replayed) accumulates the
+    same gradients as the full replay, to the order of the atomic sums; the forward's
+    values are 0 or 1 only at |d| >= 1, so umbra and fully lit rays are the ones skipped."""
+    shape, D = (176, 200), 20.0
+    h = torch.from_numpy(rough(shape, 41, 90.0)).cuda()
+    e, az = math.radians(1.1), 2.9
+    params = ss.Params(radius_m=R, mode=mode, uniform_step=step)
+    s = ss.shadow_cast(h, D, e, az, RL, params)
+    g = torch.from_numpy(np.random.default_rng(13).standard_normal(shape).astype(np.float32)).cuda()
+    gh1, gs1 = ss.shadow_cast_backward(h, D, e, az, g, RL, params)
+    gh2, gs2 = ss.shadow_cast_backward_penumbra(h, D, e, az, s, g, RL, params)
+    torch.cuda.synchronize()
+    frac_skip = float(((s == 0) | (s == 1)).float().mean())
+    print("rays skipped", frac_skip)
+    assert 0.05 < frac_skip < 0.999
+    a, b = gh1.double(), gh2.double()
+    assert float(a.norm()) > 0
+    assert float((a - b).norm()) <= 1e-5 * float(a.norm())
+    assert torch.allclose(gs1, gs2, rtol=1e-6, atol=1e-9 * float(gs1.abs().max()) + 1e-12)

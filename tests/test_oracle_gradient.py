@@ -166,3 +166,31 @@ def test_points_height_gradient_matches_finite_differences(orc, radius):
         checked += 1
         origin += int(int(lin) in taps and abs(fd) > 1e-3)
     assert checked >= 25 and origin >= 8
+
+
+def test_sun_term_scale_bounds_the_sum(orc):
+    """The absolute sums of the per-ray sun terms bound the sun gradient itself, and equal
+    it when every upstream gradient has the sign of its ray's derivative."""
+    import math as m
+    from oracle import grad_ref
+    from parity import well_conditioned
+    rng = np.random.default_rng(4)
+    h = (rng.standard_normal((40, 48)) * 60.0).astype(np.float32)
+    p = orc.Params(48, 40, 20.0, 1737400.0, m.radians(1.2), 0.7, m.radians(0.267))
+    s, _, tr = orc.shadow(h, p, trace=True)
+    mask = (well_conditioned(tr) & (s.reshape(-1) > 0) & (s.reshape(-1) < 1)).astype(float)
+    g = rng.standard_normal(s.size) * mask
+    _, ge, ga, _ = grad_ref.reference_gradient(h, p, tr, g)
+    se, sa = grad_ref.sun_term_scale(h, p, tr, g)
+    assert abs(ge) <= se * (1 + 1e-12) and abs(ga) <= sa * (1 + 1e-12) and se > 0
+    # with g_r = sign(ds_r/de) the elevation sum is its own absolute sum
+    import torch
+    from torch.func import jvp
+    ht = torch.tensor(h.astype(np.float64))
+    a0 = torch.tensor(0.7, dtype=torch.float64)
+    _, dse = jvp(lambda e: grad_ref.shadow_on_branch(ht, e, a0, p, tr), (torch.tensor(m.radians(1.2), dtype=torch.float64),),
+                 (torch.tensor(1.0, dtype=torch.float64),))
+    g2 = np.sign(dse.numpy()) * mask
+    _, ge2, _, _ = grad_ref.reference_gradient(h, p, tr, g2)
+    se2, _ = grad_ref.sun_term_scale(h, p, tr, g2)
+    assert abs(ge2 - se2) <= 1e-9 * se2
