@@ -340,6 +340,22 @@ int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles, const ss_s
                                int32_t n_suns, const ss_params* params, float* const* d_shadow,
                                void* d_workspace, int64_t workspace_bytes, void* stream);
 
+/* ss_shadow_cast_batched for callers that cannot allocate device memory or
+ * hand over a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same work and bit-identical outputs,
+ * with the tables kept in a library-owned device array of
+ * SS_NOALLOC_SCRATCH_BYTES per GPU (allocated with the library, held until the
+ * process ends).  The call allocates nothing and never waits.  Batches whose
+ * ss_batched_workspace_bytes(n_tiles, n_suns) exceeds the array get
+ * SS_ERR_WORKSPACE before anything is enqueued (2 MiB holds about 1900
+ * (tile, sun) pairs).  Every call on one GPU uses that GPU's one array, so
+ * calls on one GPU must not overlap in time (order them on one stream or with
+ * events); overlapping calls race on the tables. */
+#define SS_NOALLOC_SCRATCH_BYTES (2u << 20)
+int32_t ss_shadow_cast_batched_noalloc(const ss_tile* tiles, int32_t n_tiles, const ss_sun* suns,
+                                       int32_t n_suns, const ss_params* params,
+                                       float* const* d_shadow, void* stream);
+
 /* A captured HIP graph of the batched call for fixed buffers.  Create picks the
  * ray-tile shape and mipmap fusion depth by timing the candidates on these
  * inputs (it synchronises `stream` while tuning), then captures the maxmip

@@ -13,6 +13,7 @@ SS_ERR_INVALID_ARG = -1
 SS_ERR_HIP = -2
 SS_ERR_WORKSPACE = -3
 SS_ERR_UNSUPPORTED = -4
+SS_NOALLOC_SCRATCH_BYTES = 2 << 20
 SS_MODE_DP = 0
 SS_MODE_UNIFORM = 1
 SS_MODE_EXACT = 2
@@ -86,6 +87,9 @@ SIGNATURES = {
     "ss_shadow_cast_batched": (C.c_int32, [C.POINTER(SSTile), C.c_int32, C.POINTER(SSSun),
                                            C.c_int32, C.POINTER(SSParams), C.c_void_p, C.c_void_p,
                                            C.c_int64, C.c_void_p]),
+    "ss_shadow_cast_batched_noalloc": (C.c_int32, [C.POINTER(SSTile), C.c_int32,
+                                                   C.POINTER(SSSun), C.c_int32,
+                                                   C.POINTER(SSParams), C.c_void_p, C.c_void_p]),
     "ss_batched_plan_create": (C.c_int32, [C.POINTER(SSTile), C.c_int32, C.POINTER(SSSun),
                                            C.c_int32, C.POINTER(SSParams), C.c_void_p, C.c_void_p,
                                            C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]),

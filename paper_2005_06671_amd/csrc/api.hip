@@ -814,6 +814,47 @@ extern "C" int32_t ss_shadow_cast_batched(const ss_tile* tiles, int32_t n_tiles,
 }
 
 // ------------------------------------------------------------------------
+// Batched call without a caller workspace: the tables live in a fixed
+// library-owned device array (one per GPU, held until the process ends).
+// ------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[SS_NOALLOC_SCRATCH_BYTES];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (in host code the array's name is only a stand-in).
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+static int32_t scratch_on_current_device(unsigned char** out) {
+  int dev = 0;
+  SS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return SS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    SS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return SS_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return SS_OK;
+}
+
+extern "C" int32_t ss_shadow_cast_batched_noalloc(const ss_tile* tiles, int32_t n_tiles,
+                                                  const ss_sun* suns, int32_t n_suns,
+                                                  const ss_params* params, float* const* d_shadow,
+                                                  void* stream) {
+  int32_t rc = check_batch(tiles, n_tiles, suns, n_suns, params, d_shadow);
+  if (rc) return rc;
+  if (n_tiles == 0 || n_suns == 0) return SS_OK;
+  if (ss_batched_workspace_bytes(n_tiles, n_suns) > (int64_t)SS_NOALLOC_SCRATCH_BYTES)
+    return SS_ERR_WORKSPACE;
+  unsigned char* ws = nullptr;
+  if ((rc = scratch_on_current_device(&ws))) return rc;
+  return batched_on(tiles, n_tiles, suns, n_suns, params, d_shadow, ws, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------------
 // Tuner and captured plan.
 // ------------------------------------------------------------------------
 
