@@ -147,9 +147,14 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, counters_dir, out_dir):
         lines.append(f"{r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.2f}")
     with open(os.path.join(out_dir, "bench_tile_kernel_stats.txt"), "w") as f:
-        f.write("# rocprofv3 --kernel-trace --stats summary of the tile benchmark\n")
-        f.write("# command: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
-                "python bench.py --steps 5 --warmup 1 --no-cpu --no-extras --dem-cache /tmp/dem_tile.npy\n")
+        f.write("# rocprofv3 --kernel-trace --stats summary of the tile benchmark (the timed step: "
+                "20 graph replays after 5 warm-up ones; the plan's choices come from the tuner "
+                "cache a previous run wrote, so no tuning launch is traced)\n")
+        f.write("# command: SS_TUNE_CACHE=/tmp/ss_tune.jsonl python bench.py --steps 2 --warmup 1 "
+                "--no-cpu --no-extras --dem-cache /tmp/dem_tile.npy; SS_TUNE_CACHE=/tmp/ss_tune.jsonl "
+                "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- "
+                "python bench.py --steps 20 --warmup 5 --no-cpu --no-extras --dem-cache "
+                "/tmp/dem_tile.npy\n")
         f.write("\n".join(lines) + "\n")
 
     def per_kernel(d, counter):
@@ -178,9 +183,10 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, counters_dir, out_dir):
         k = out["kernels"][dp[0]]
         out["hbm_bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
         out["kernel"] = dp[0]
-    out["command"] = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-include-regex 'ss::|copy' "
-                      "--output-format csv -d <dir> -o bench -- python bench.py --steps 1 --warmup 0 "
-                      "--no-cpu --no-extras --calibrate-copy --dem-cache /tmp/dem_tile.npy")
+    out["command"] = ("SS_TUNE_CACHE=/tmp/ss_tune.jsonl rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) "
+                      "--kernel-include-regex 'ss::|copy' --output-format csv -d <dir> -o bench -- "
+                      "python bench.py --steps 1 --warmup 0 --no-cpu --no-extras --calibrate-copy "
+                      "--dem-cache /tmp/dem_tile.npy")
     with open(os.path.join(out_dir, TRAFFIC_FILE), "w") as f:
         json.dump(out, f, indent=1)
     if counters_dir:
@@ -220,10 +226,11 @@ def summarize_counters(csv_path, out_dir):
                                            if "TCC_HIT_sum" in v and "TCC_MISS_sum" in v
                                            else None)}}, f, indent=1)
     with open(os.path.join(out_dir, COUNTERS_FILE), "w") as f:
-        f.write("# rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU "
-                "SQ_INSTS_VALU_TRANS_F32 TCC_HIT_sum TCC_MISS_sum --kernel-include-regex "
-                "'flat_kernel|batched_kernel|shadow_kernel' --output-format csv -d <dir> -o bench -- python "
-                "bench.py --steps 1 --warmup 0 --no-cpu --no-extras --dem-cache /tmp/dem_tile.npy\n")
+        f.write("# SS_TUNE_CACHE=/tmp/ss_tune.jsonl rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU "
+                "SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_INSTS_VALU_TRANS_F32 TCC_HIT_sum "
+                "TCC_MISS_sum --kernel-include-regex 'flat_kernel|shadow_kernel' --output-format csv "
+                "-d <dir> -o bench -- python bench.py --steps 1 --warmup 0 --no-cpu --no-extras "
+                "--dem-cache /tmp/dem_tile.npy\n")
         f.write("\n".join(lines) + "\n")
 
 
