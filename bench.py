@@ -396,9 +396,10 @@ def leg_gather(ss, dev, n_rays, src_floats, roof, iters=64, n_threads=1 << 21):
     cache line), from the library's gather probe (indices generated in the
     kernel, eight loads in flight per lane) over a buffer the size of the
     tile's heightfield plus mipmap, inside 1 MiB windows (L2-resident) and
-    16 KiB windows (L1-resident); against the descent's own gather rate (one
-    per lower bound, four per bilinear sample), whose 8 x 8 ray tiles keep
-    neighbouring lanes on shared cache lines."""
+    16 KiB windows (L1-resident); the rate of coherent gathers (each wavefront
+    reads an 8 x 8 patch of a tile-sized image per step, the pattern of the
+    descent's 8 x 8 ray tiles); and the descent's own gather rate (one per lower
+    bound, four per bilinear sample) against both."""
     import torch
     src = torch.rand(src_floats, device=dev)
     out = torch.empty(n_threads, dtype=torch.float32, device=dev)
@@ -407,10 +408,20 @@ def leg_gather(ss, dev, n_rays, src_floats, roof, iters=64, n_threads=1 << 21):
         ss.probe_gather(src, win, iters, n_threads, out)
         t = min(_timed(lambda: ss.probe_gather(src, win, iters, n_threads, out), 3))
         res["incoherent_" + name + "_gathers_per_s"] = n_threads * iters / (t / 1e3)
+    # coherent: a wavefront reads one 8 x 8 patch of a tile-sized image per step, as the
+    # descent's 8 x 8 ray tiles read neighbouring texels (the measured L2-side ceiling for
+    # that pattern)
+    side = int(math.isqrt(src_floats))
+    img = src[:side * side].view(side, side)
+    ss.probe_gather_tiles(img, iters, n_threads, out)
+    t = min(_timed(lambda: ss.probe_gather_tiles(img, iters, n_threads, out), 3))
+    res["coherent_8x8_patch_gathers_per_s"] = n_threads * iters / (t / 1e3)
     res["descent_gathers_per_s"] = ((roof["lb_evals_per_ray"] + 4.0 * roof["samples_per_ray"])
                                     * n_rays / (roof["avg_launch_ms"] / 1e3))
     res["descent_over_incoherent_1MiB"] = (res["descent_gathers_per_s"]
                                            / res["incoherent_window_1MiB_gathers_per_s"])
+    res["descent_over_coherent_8x8"] = (res["descent_gathers_per_s"]
+                                        / res["coherent_8x8_patch_gathers_per_s"])
     return res
 
 

@@ -387,6 +387,16 @@ int32_t ss_batched_plan_destroy(ss_plan* plan);
 int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t window, int32_t iters,
                         float* d_out, int64_t n_threads, void* stream);
 
+/* Coherent gather probe, the access pattern of the shadow rays' 8 x 8 ray
+ * tiles (not part of the method): n_threads lanes (a multiple of 256) each sum
+ * `iters` floats (rounded up to a multiple of 8); the 64 lanes of a wavefront
+ * read one 8 x 8 patch of the [rows][width] image d_src per step (lane k at
+ * row k / 8, column k % 8 of the patch), the patch origin pseudo-random per
+ * wavefront and step; width, rows in 8..65536.  d_out[n_threads] receives the
+ * sums.  Rate = n_threads iters / time 4-byte gathers per second. */
+int32_t ss_probe_gather_tiles(const float* d_src, int32_t width, int32_t rows, int32_t iters,
+                              float* d_out, int64_t n_threads, void* stream);
+
 /* FP32 VALU probe used to check the arithmetic peak a roofline divides by (not
  * part of the method): n_workgroups x 256 lanes each run 32 x iters non-packed
  * FP32 FMAs in eight independent chains; d_out[n_workgroups * 256] receives

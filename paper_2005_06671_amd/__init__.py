@@ -8,7 +8,7 @@ from .api import (  # noqa: F401
     shadow_cast_batched, batched_workspace_bytes, BatchedPlan, SUN_RADIUS_RAD,
     bound_build, bound_floats, bound_level_offset, bound_unpack,
     shadow_cast_save, shadow_cast_backward_saved, shadow_cast_backward_penumbra, probe_gather,
-    probe_valu, shadow_points,
+    probe_gather_tiles, probe_valu, shadow_points,
     Camera, view_cast, frame, Frame, resample, stitch, shadow_points_image,
     shadow_points_backward, ShadowPoints, shadow_at,
 )

@@ -112,6 +112,8 @@ SIGNATURES = {
                                 C.c_double, C.c_void_p]),
     "ss_probe_gather": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
                                     C.c_int64, C.c_void_p]),
+    "ss_probe_gather_tiles": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                          C.c_void_p, C.c_int64, C.c_void_p]),
     "ss_probe_valu": (C.c_int32, [C.c_int32, C.c_int64, C.c_void_p, C.c_void_p]),
     "ss_status_string": (C.c_char_p, [C.c_int32]),
 }

@@ -460,6 +460,24 @@ def shadow_points_image(h: torch.Tensor, texel_m: float, elev: float, azim: floa
     return out
 
 
+def probe_gather_tiles(src: torch.Tensor, iters: int = 64, n_threads: int = 1 << 21,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+    """Coherent gather probe (ss_probe_gather_tiles): each wavefront reads 8 x 8 patches of the
+    2-D float32 image src; returns the per-lane sums."""
+    if (not src.is_cuda or src.dtype != torch.float32 or not src.is_contiguous()
+            or src.dim() != 2):
+        raise ValueError("src must be a contiguous 2-D float32 CUDA tensor")
+    if out is None:
+        out = torch.empty(n_threads, dtype=torch.float32, device=src.device)
+    elif out.numel() < n_threads:
+        raise ValueError("out is too small")
+    L.check("ss_probe_gather_tiles",
+            L.lib().ss_probe_gather_tiles(src.data_ptr(), int(src.shape[1]), int(src.shape[0]),
+                                          int(iters), out.data_ptr(), int(n_threads),
+                                          _stream(src.device)))
+    return out
+
+
 def probe_valu(iters: int = 4096, n_workgroups: int = 8192, device=None,
                out: torch.Tensor | None = None) -> torch.Tensor:
     """FP32 VALU probe (ss_probe_valu): 32 * iters FMAs per lane over n_workgroups x 256 lanes;

@@ -567,6 +567,16 @@ extern "C" int32_t ss_probe_gather(const float* d_src, int64_t n_floats, int64_t
   return SS_OK;
 }
 
+extern "C" int32_t ss_probe_gather_tiles(const float* d_src, int32_t width, int32_t rows,
+                                         int32_t iters, float* d_out, int64_t n_threads,
+                                         void* stream) {
+  if (!d_src || !d_out || width < 8 || rows < 8 || width > 65536 || rows > 65536 || iters < 1)
+    return SS_ERR_INVALID_ARG;
+  if (n_threads < 256 || n_threads % 256 != 0 || n_threads / 256 > 0x7fffffffLL) return SS_ERR_INVALID_ARG;
+  SS_HIP(launch_gather_tiles_probe(d_src, width, rows, iters, d_out, n_threads, (hipStream_t)stream));
+  return SS_OK;
+}
+
 extern "C" int32_t ss_probe_valu(int32_t iters, int64_t n_workgroups, float* d_out, void* stream) {
   if (!d_out || iters < 1 || n_workgroups < 1 || n_workgroups > 0x7fffffffLL) return SS_ERR_INVALID_ARG;
   SS_HIP(launch_valu_probe(iters, n_workgroups, d_out, (hipStream_t)stream));

@@ -125,6 +125,8 @@ hipError_t launch_resample(const ResampleK& K, hipStream_t stream);
 // Gather throughput probe (measurement only).
 hipError_t launch_gather_probe(const float* src, long long n_floats, long long window, int iters,
                                float* out, long long n_threads, hipStream_t stream);
+hipError_t launch_gather_tiles_probe(const float* src, int width, int rows, int iters, float* out,
+                                     long long n_threads, hipStream_t stream);
 hipError_t launch_valu_probe(int iters, long long n_workgroups, float* out, hipStream_t stream);
 
 }  // namespace ss

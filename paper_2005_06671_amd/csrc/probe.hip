@@ -47,6 +47,42 @@ hipError_t launch_gather_probe(const float* src, long long n_floats, long long w
   return hipGetLastError();
 }
 
+// Coherent gathers, as the shadow rays issue them: the 64 lanes of a
+// wavefront read one 8 x 8 patch of a [rows][width] image (lane k: row k / 8,
+// column k % 8), the patch origin drawn per wavefront and step from a
+// wave-uniform xorshift sequence, eight patches in flight per lane.
+__global__ __launch_bounds__(256) void gather_tiles_probe_kernel(const float* __restrict__ src,
+                                                                 unsigned width, unsigned span_x,
+                                                                 unsigned span_y, int iters,
+                                                                 float* __restrict__ out) {
+  const unsigned lane = threadIdx.x & 63u;
+  const unsigned wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+  unsigned x = wave * 2654435761u + 97u;
+  x ^= x >> 16;
+  const unsigned lx = lane & 7u, ly = lane >> 3;
+  float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < iters; k += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      x ^= x << 13;
+      x ^= x >> 17;
+      x ^= x << 5;
+      const unsigned px = (x & 0xffffu) % span_x, py = (x >> 16) % span_y;
+      acc[q] += src[(size_t)(py + ly) * width + px + lx];
+    }
+  }
+  out[blockIdx.x * 256u + threadIdx.x] =
+      ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+hipError_t launch_gather_tiles_probe(const float* src, int width, int rows, int iters, float* out,
+                                     long long n_threads, hipStream_t stream) {
+  hipLaunchKernelGGL(gather_tiles_probe_kernel, dim3((unsigned)(n_threads / 256)), dim3(256), 0,
+                     stream, src, (unsigned)width, (unsigned)(width - 7), (unsigned)(rows - 7),
+                     iters, out);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void valu_probe_kernel(int iters, float a, float b,
                                                          float* __restrict__ out) {
   const float x = (float)threadIdx.x * 1e-3f;

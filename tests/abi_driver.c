@@ -118,6 +118,11 @@ int main(void) {
          SS_ERR_INVALID_ARG);
   EXPECT(ss_shadow_cast_backward_saved(&t, &sun, &p, NULL, FAKE(0x400000), FAKE(0x500000),
                                        (double*)FAKE(0x600000), NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_cast_backward_penumbra(&t, &sun, &p, NULL, FAKE(0x400000), FAKE(0x500000),
+                                          (double*)FAKE(0x600000), NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_cast_backward_penumbra(&t, &sun, &p, FAKE(0x400000), FAKE(0x400000),
+                                          FAKE(0x500000), (double*)FAKE(0x600004), NULL) ==
+         SS_ERR_INVALID_ARG);
   EXPECT(ss_shadow_points(&t, &sun, &p, FAKE(0x400004), 10, FAKE(0x500000), NULL) ==
          SS_ERR_INVALID_ARG);
   EXPECT(ss_shadow_points(&t, &sun, &p, NULL, 10, FAKE(0x500000), NULL) == SS_ERR_INVALID_ARG);
@@ -148,6 +153,10 @@ int main(void) {
                                 NULL) == SS_ERR_WORKSPACE);
   EXPECT(ss_shadow_cast_batched(tiles, 2, suns, 2, &p, NULL, FAKE(0x800000), ws, NULL) ==
          SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_cast_batched_noalloc(tiles, -1, suns, 2, &p, (float* const*)outs, NULL) ==
+         SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_cast_batched_noalloc(tiles, 2, suns, 2, &p, NULL, NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_shadow_cast_batched_noalloc(tiles, 0, suns, 2, &p, NULL, NULL) == SS_OK);
   q = p;
   q.mode = SS_MODE_EXACT;
   tiles[1].bound = NULL;  /* the exact mode needs every tile's tap-bound buffer */
@@ -202,6 +211,11 @@ int main(void) {
 
   /* probe */
   EXPECT(ss_probe_gather(NULL, 1024, 0, 8, FAKE(0x200000), 256, NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_probe_gather_tiles(NULL, 64, 64, 8, FAKE(0x200000), 256, NULL) == SS_ERR_INVALID_ARG);
+  EXPECT(ss_probe_gather_tiles(FAKE(0x100000), 7, 64, 8, FAKE(0x200000), 256, NULL) ==
+         SS_ERR_INVALID_ARG);
+  EXPECT(ss_probe_gather_tiles(FAKE(0x100000), 64, 64, 8, FAKE(0x200000), 255, NULL) ==
+         SS_ERR_INVALID_ARG);
   EXPECT(ss_probe_valu(0, 8, FAKE(0x200000), NULL) == SS_ERR_INVALID_ARG);
   EXPECT(ss_probe_valu(16, 8, NULL, NULL) == SS_ERR_INVALID_ARG);
 

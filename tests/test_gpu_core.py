@@ -254,3 +254,30 @@ def test_sun_below_local_horizon(ss):
     h = rough((256, 256), 8, 30.0)
     p = oracle.Params(256, 256, 128.0, R, math.radians(0.2), 1.0, RL, max_len_m=20000.0)
     assert_parity(compare(h, p, run(ss, h, p), label="low sun big texels"))
+
+
+def test_gather_tiles_probe_reads_its_patches(ss):
+    """The coherent gather probe reads exactly the 8 x 8 patches its definition names: lane
+    k of a wavefront sums src[(py + k // 8) * width + px + k % 8] over its steps, with the
+    patch origins drawn from the wavefront's xorshift sequence (recomputed here)."""
+    width, rows, iters, n_threads = 40, 24, 8, 512
+    src = torch.arange(width * rows, dtype=torch.float32, device=dev()).view(rows, width) * 0.25
+    out = ss.probe_gather_tiles(src, iters, n_threads)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    s_np = src.cpu().numpy().reshape(-1).astype(np.float64)
+    M = 0xFFFFFFFF
+    for tid in range(n_threads):
+        lane, wave = tid & 63, tid >> 6
+        x = (wave * 2654435761 + 97) & M
+        x ^= x >> 16
+        acc = [0.0] * 8
+        for k in range(0, iters, 8):
+            for q in range(8):
+                x ^= (x << 13) & M
+                x ^= x >> 17
+                x ^= (x << 5) & M
+                px, py = (x & 0xFFFF) % (width - 7), (x >> 16) % (rows - 7)
+                acc[q] += s_np[(py + (lane >> 3)) * width + px + (lane & 7)]
+        ref = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]))
+        assert abs(got[tid] - ref) <= 1e-3, (tid, got[tid], ref)
