@@ -1,7 +1,8 @@
 """FP64 CPU reference oracle for the soft-shadow hot path (TEST INFRASTRUCTURE).
 
-Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
-leg may import this package.  It shares no code with the HIP library and never
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
+leg (``cpu_baseline`` and the host timings beside it, skipped with ``--no-cpu``)
+may import this package.  It shares no code with the HIP library and never
 reads anything the GPU path produced.
 
 The numerics live in plain C (``oracle.c``, ``alternatives.c``, ``view.c``, ``resample.c``), compiled with
