@@ -19,9 +19,11 @@
  *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
  *    work on it: they return before the GPU finishes and never synchronise the
  *    device, except where a function says otherwise.  Apart from
- *    ss_batched_plan_create, every call that takes a stream only launches
- *    kernels on it (no allocation, no host wait, no memset or copy node), so
- *    it may be recorded into a caller's HIP graph by stream capture.
+ *    ss_batched_plan_create (which tunes and synchronises) and
+ *    ss_batched_plan_launch (which launches the plan's own graph), every call
+ *    that takes a stream only launches kernels on it (no allocation, no host
+ *    wait, no memset or copy node), so it may be recorded into a caller's HIP
+ *    graph by stream capture.
  *  - Return value: SS_OK (0) or a negative SS_ERR_* status; arguments are
  *    validated on the host before anything is enqueued, so an error leaves
  *    every output untouched.  No C++ exception crosses the ABI.
