@@ -1,5 +1,11 @@
-// Persistent batched kernel: many suns over tiles of uneven size in one launch.
+// The batched call: many suns over tiles of uneven size in one launch, as a
+// flat grid over every ray block of every (tile, sun) pair (flat_kernel, the
+// default) or a persistent kernel with per-XCD queues (batched_kernel); and
+// the staging of the batch's per-pair set-up into the workspace through kernel
+// arguments (stage_kernel, expand_kernel), so the call needs no host buffer,
+// no copy and no wait.
 //
+// Persistent form:
 // Items are groups of ray blocks of a (tile, sun) pair.  Each pair's items are
 // split into SS_NXCD contiguous row bands, and XCD x has its own queue: band x
 // of every pair, pairs in tile-major, sun-minor order.  A workgroup takes the
@@ -245,7 +251,7 @@ hipError_t launch_stage(void* d_dst, const void* h_src, size_t bytes, hipStream_
   const unsigned* src = static_cast<const unsigned*>(h_src);
   unsigned* dst = static_cast<unsigned*>(d_dst);
   const size_t words = bytes / 4;
-  StageChunk c;
+  StageChunk c = {};
   for (size_t k = 0; k < words; k += SS_STAGE_WORDS) {
     c.n = (unsigned)(words - k < SS_STAGE_WORDS ? words - k : SS_STAGE_WORDS);
     memcpy(c.w, src + k, c.n * sizeof(unsigned));
