@@ -304,6 +304,81 @@ __global__ __launch_bounds__(256) void adjoint_kernel(TileK T, SunTrig st,
   }
 }
 
+// Adjoint given the forward's values on large tiles (ss_shadow_cast_backward_
+// penumbra): a workgroup takes SS_PEN_BLOCKS consecutive ray blocks (its id
+// remapped as the other per-tile kernels remap theirs), lists in LDS the rays
+// whose s lies strictly inside (0, 1) and whose upstream gradient is nonzero
+// (a ballot per wavefront, so neighbouring rays stay neighbours in the list),
+// then replays only those, 256 at a time, so the replaying wavefronts run
+// full.  It pays where penumbra is sparse and the launch has many workgroups
+// per device-full to balance the uneven lists (the launcher's threshold);
+// smaller launches keep adjoint_kernel's per-lane skip.
+#define SS_PEN_BLOCKS 8
+
+template <bool SPHERE, int MODE>
+__global__ __launch_bounds__(256) void adjoint_penumbra_kernel(TileK T, SunTrig st,
+                                                               const float* __restrict__ gs,
+                                                               const float* __restrict__ sfwd,
+                                                               float* __restrict__ gh,
+                                                               double* __restrict__ gsun, int nbx,
+                                                               int nblocks) {
+  __shared__ double red[2][4];
+  __shared__ int tab[SS_MAXLEV];
+  __shared__ unsigned list[SS_PEN_BLOCKS * 256];
+  __shared__ unsigned count;
+  if (threadIdx.x == 0) count = 0u;
+  if (MODE == SS_MODE_EXACT) bound_tab_fill(T, tab);
+  __syncthreads();
+  const int grp = xcd_remap_grouped((int)blockIdx.x, (int)gridDim.x, T.wg_group);
+  const int lane = threadIdx.x & 63;
+  for (int g = 0; g < SS_PEN_BLOCKS; ++g) {
+    const int vb = grp * SS_PEN_BLOCKS + g;
+    bool take = false;
+    int li = 0, lj = 0;
+    if (vb < nblocks) {
+      coords_of<8>(vb, nbx, li, lj);
+      if (li < T.RW && lj < T.RH) {
+        const int k = lj * T.RW + li;
+        const float sv = sfwd[k];
+        take = gs[k] != 0.0f && sv != 0.0f && sv != 1.0f;
+      }
+    }
+    const unsigned long long m = __ballot(take);
+    if (m) {
+      unsigned base = 0u;
+      if (lane == 0) base = atomicAdd(&count, (unsigned)__popcll(m));
+      base = __shfl(base, 0, 64);
+      if (take)
+        list[base + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] =
+            (unsigned)li | ((unsigned)lj << 16);
+    }
+  }
+  __syncthreads();
+  const unsigned n = count;
+  double ge = 0.0, ga = 0.0;
+  for (unsigned q = threadIdx.x; q < n; q += 256u) {
+    const unsigned e = list[q];
+    adjoint_ray<SPHERE, MODE, false>(T, st, (int)(e & 0xffffu), (int)(e >> 16), gs, nullptr,
+                                     nullptr, gh, ge, ga, tab);
+  }
+  ge = wave_sum_f64(ge);
+  ga = wave_sum_f64(ga);
+  const int wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = ge;
+    red[1][wave] = ga;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double se = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    const double sa = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    if (se != 0.0 || sa != 0.0) {
+      atomicAdd(&gsun[0], se);
+      atomicAdd(&gsun[1], sa);
+    }
+  }
+}
+
 // Shadow rays from arbitrary surface points: point k at continuous texel
 // coordinates xy[k] (clamped to the tile), on the bilinear terrain there.
 template <bool SPHERE, int MODE>
@@ -597,7 +672,13 @@ template <bool SPHERE, int MODE>
 static void adjoint_launch(const TileK& T, const SunTrig& st, const float* gs, const int* sample,
                            const float* sfwd, float* gh, double* gsun, int nbx, int nb,
                            hipStream_t stream) {
-  if (sample)
+  // the compacting form once the launch has at least 16 device-fulls of its workgroups
+  // (2^18 ray blocks, 8192^2 rays): fewer, and the uneven lists leave CUs idle at the end
+  if (sfwd && !sample && (long long)nb >= 16LL * SS_PEN_BLOCKS * T.wg_group)
+    hipLaunchKernelGGL((adjoint_penumbra_kernel<SPHERE, MODE>),
+                       dim3((nb + SS_PEN_BLOCKS - 1) / SS_PEN_BLOCKS), dim3(256), 0, stream, T,
+                       st, gs, sfwd, gh, gsun, nbx, nb);
+  else if (sample)
     hipLaunchKernelGGL((adjoint_kernel<SPHERE, 8, MODE, true>),
                        dim3((nb + AdjBlocks<true>::n - 1) / AdjBlocks<true>::n), dim3(256), 0,
                        stream, T, st, gs, sample, sfwd, gh, gsun, nbx, nb);

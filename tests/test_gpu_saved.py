@@ -126,3 +126,34 @@ def test_penumbra_backward_equals_full_replay(ss, mode, step):
     assert float(a.norm()) > 0
     assert float((a - b).norm()) <= 1e-5 * float(a.norm())
     assert torch.allclose(gs1, gs2, rtol=1e-6, atol=1e-9 * float(gs1.abs().max()) + 1e-12)
+
+
+def test_penumbra_backward_compacting_form_on_a_large_tile(ss):
+    """On launches of 2^18 ray blocks or more (an 8192^2 tile) the penumbra adjoint lists the
+    contributing rays of each workgroup's blocks and replays only those; the gradients still
+    equal the full replay's to the order of the atomic sums."""
+    n, D = 8192, 4.0
+    dev = torch.device("cuda:0")
+    y, x = torch.meshgrid(torch.arange(n, device=dev, dtype=torch.float32),
+                          torch.arange(n, device=dev, dtype=torch.float32), indexing="ij")
+    gen = np.random.default_rng(17)
+    h = torch.zeros((n, n), device=dev)
+    for k in range(6):
+        f, th, ph = gen.uniform(0.002, 0.05), gen.uniform(0, 2 * math.pi), gen.uniform(0, 6)
+        h += 300.0 / (k + 1) * torch.sin(f * (x * math.cos(th) + y * math.sin(th)) + ph)
+    del x, y
+    e, az = math.radians(0.9), 1.3
+    params = ss.Params(radius_m=R, max_len_m=8000.0)
+    mm = ss.maxmip(h)
+    s = ss.shadow_cast(h, D, e, az, RL, params, mm=mm)
+    g = torch.randn((n, n), generator=torch.Generator(device=dev).manual_seed(3), device=dev)
+    gh1, gs1 = ss.shadow_cast_backward(h, D, e, az, g, RL, params, mm=mm)
+    gh2, gs2 = ss.shadow_cast_backward_penumbra(h, D, e, az, s, g, RL, params, mm=mm)
+    torch.cuda.synchronize()
+    pen = float(((s > 0) & (s < 1)).float().mean())
+    print("penumbra fraction", pen)
+    assert 0.005 < pen < 0.9
+    a, b = gh1.double(), gh2.double()
+    assert float(a.norm()) > 0
+    assert float((a - b).norm()) <= 1e-5 * float(a.norm())
+    assert torch.allclose(gs1, gs2, rtol=1e-6, atol=1e-9 * float(gs1.abs().max()) + 1e-12)
